@@ -1,0 +1,188 @@
+/*
+ * fvk -- Krylov-vector engine for the linear-stability / Newton solver of
+ * buoyancy convection in a laterally heated cube (Gelfgat, arXiv:1905.11601),
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  All `double *` arguments named base, x, y, F, V, p_out, w are DEVICE
+ * pointers to caller-owned, contiguous FP64 buffers (e.g. torch tensors) in
+ * the layout reported by fvk_layout(); `h_col`, `Q`, `out` and the grid-query
+ * arrays are HOST pointers.  The context owns every workspace it needs
+ * (allocated once in fvk_create, sized for the grid).  All work is enqueued
+ * on the HIP stream given to fvk_create / fvk_set_stream; calls that return
+ * host values synchronise that stream.  A context is not thread-safe; use one
+ * per stream.  Errors are status codes with a message from fvk_last_error();
+ * no call aborts or throws.
+ *
+ * Layout of a 4-field vector (Krylov vector, base flow, residual):
+ *   field f in {0:u, 1:v, 2:w, 3:T} starts at f * field_len doubles;
+ *   each field is a (nz+2) x (ny+2) x (nx+2) array, x fastest:
+ *   element (i, j, k) at ((k * (ny+2)) + j) * (nx+2) + i.
+ *   u lives on x-faces (i = 0..nx; i = 0, nx are the walls; i = nx+1 unused),
+ *   v on y-faces, w on z-faces (cyclically); T at cell centres with one wall
+ *   node per side (index 0 and n+1).  Entries that are not interior rows
+ *   (walls, edges, padding) are part of the vector; operators write them with
+ *   the values their definition gives (mostly 0).
+ *
+ * The discretisation is the second-order staggered finite-volume scheme with
+ * stored wall nodes read from Sec. 3.1 of the paper; the equations are
+ * eqs (1)-(3) in the Gr^1/2 scaling: nu = Gr^-1/2, kappa = nu / Pr, b = 1.
+ */
+#ifndef FVK_H
+#define FVK_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fvk_ctx fvk_ctx;
+
+typedef enum {
+    FVK_OK = 0,
+    FVK_EINVAL = 1,      /* bad argument (size, enum, null pointer)           */
+    FVK_ENOMEM = 2,      /* device or host allocation failed                  */
+    FVK_EHIP = 3,        /* a HIP runtime call failed                         */
+    FVK_ENOCONV = 4,     /* SIMPLE pass cap, GMRES/BiCGstab(2) or Newton limit */
+    FVK_EBREAKDOWN = 5   /* Krylov breakdown (zero norm / NaN)                */
+} fvk_status;
+
+/* Spanwise (y = 0, 1) thermal walls: eq. (6) perfectly conducting, eq. (7)
+ * perfectly insulated. */
+typedef enum { FVK_SPAN_CC = 0, FVK_SPAN_AA = 1 } fvk_span_bc;
+
+/* Face coordinates f_i = map(i / N): uniform; eq. (22) x - s sin(2 pi x)
+ * (0 <= s < 1/(2 pi)); tanh clustering (1 + tanh(s (2x - 1)) / tanh s) / 2. */
+typedef enum { FVK_GRID_UNIFORM = 0, FVK_GRID_SINE = 1, FVK_GRID_TANH = 2 } fvk_grid_kind;
+
+/* FVK_FP64: everything in FP64.  FVK_MIXED: the Poisson eigenbasis
+ * transforms of the SIMPLE pass run in FP32 (FP32 accumulation); the SIMPLE
+ * loop repeats the pass (FP64 divergence, FP64 correction) as iterative
+ * refinement until the divergence test passes.  Everything else is FP64. */
+typedef enum { FVK_FP64 = 0, FVK_MIXED = 1 } fvk_prec;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context for an nx x ny x nz finite-volume grid (each >= 2, each
+ * <= 1024).  `s` is the stretching parameter of `grid_kind`.  Builds the grid,
+ * the 1D eigendecompositions of eq. (15) (host, FP64) and allocates all
+ * device workspace.  `hip_stream` is a hipStream_t (NULL = default stream).
+ * On failure *out is NULL. */
+fvk_status fvk_create(fvk_ctx **out, int nx, int ny, int nz, int grid_kind, double s,
+                      int span_bc, double Gr, double Pr, int prec, void *hip_stream);
+fvk_status fvk_destroy(fvk_ctx *ctx);
+fvk_status fvk_set_stream(fvk_ctx *ctx, void *hip_stream);
+/* Re-derive nu = Gr^-1/2, kappa = nu / Pr, b = 1 (eqs (1)-(2)). */
+fvk_status fvk_set_params(fvk_ctx *ctx, double Gr, double Pr);
+/* Set the three coefficients directly (viscous scaling checks at Gr = 0,
+ * derivative operators dA/dGr with b = 0). */
+fvk_status fvk_set_coeffs(fvk_ctx *ctx, double nu, double kappa, double b);
+fvk_status fvk_set_precision(fvk_ctx *ctx, int prec);
+/* SIMPLE loop control (Sec. 3.1): stop when max |D v| < tol (default 1e-9,
+ * the paper's pointwise criterion), at most max_passes passes (default 10). */
+fvk_status fvk_set_simple(fvk_ctx *ctx, double tol, int max_passes);
+/* off[f] = offset (in doubles) of field f in a 4-field vector, field_len =
+ * (nx+2)(ny+2)(nz+2), n_total = 4 * field_len. */
+fvk_status fvk_layout(const fvk_ctx *ctx, size_t off[4], size_t *field_len, size_t *n_total);
+/* Host copies of one axis (0 = x, 1 = y, 2 = z): faces[0..n], centres[0..n+1]
+ * (wall nodes included), widths[0..n+1] (widths[i] = f[i] - f[i-1], ends 0).
+ * Any pointer may be NULL. */
+fvk_status fvk_grid_axis(const fvk_ctx *ctx, int axis, double *faces, double *centres,
+                         double *widths);
+const char *fvk_last_error(const fvk_ctx *ctx);
+/* Host utility used at context creation for eq. (15): eigenvalues lam[0..n)
+ * and orthonormal eigenvectors (Q row-major n x n, column q for lam[q]) of the
+ * symmetric tridiagonal matrix with diagonal diag[0..n) and off-diagonal
+ * off[0..n-1), by the implicit QL algorithm.  Host pointers; no GPU needed. */
+fvk_status fvk_tridiag_eig(int n, const double *diag, const double *off, double *lam, double *Q);
+
+/* ------------------------------------------------------------- operators */
+
+/* F(U, Theta): residual of the steady eqs (1)-(2) at interior rows (Sec. 3.1
+ * Newton step 2), pressure omitted; other entries 0.  base = (U, V, W, Theta)
+ * with the inhomogeneous wall values of eqs (4)-(7) in its wall nodes.
+ * project != 0 returns P F (SIMPLE projection of the velocity part,
+ * temperature projection of eq. (21) of the T part). */
+fvk_status fv_residual(fvk_ctx *ctx, const double *base, double *F, int project);
+
+/* y = J x: the Jacobian of F about `base` (eqs (8)-(9)) at interior rows,
+ * other entries 0 (transpose = 0); y = J^T x, the Euclidean transpose over
+ * all stored entries (transpose = 1).  x and y must not overlap. */
+fvk_status fv_jacvec(fvk_ctx *ctx, const double *base, const double *x, double *y,
+                     int transpose);
+
+/* y = P x (transpose = 0): the SIMPLE projection of the velocity part
+ * (eq. (13): divergence-free, homogeneous no-slip) and the temperature
+ * projection of eq. (21) (homogeneous thermal BCs); y = P^T x (transpose = 1).
+ * x == y is allowed. */
+fvk_status fvk_project(fvk_ctx *ctx, const double *x, double *y, int transpose);
+
+/* The next Krylov vector, eqs (11)-(13): y = A x = P J x (transpose = 0) or
+ * y = A^T x = J^T P^T x (transpose = 1).  p_out (nullable, device, nx*ny*nz
+ * doubles, cell order x fastest) receives the accumulated pressure
+ * correction.  If `passes` or `max_div` is non-NULL the call synchronises and
+ * reports the SIMPLE pass count and the final max |D v|; if both are NULL the
+ * call is asynchronous and the divergence check is recorded on the device
+ * (fvk_simple_stats).  Returns FVK_ENOCONV when the pass cap is hit.
+ * x and y must not overlap. */
+fvk_status simple_krylov_vec(fvk_ctx *ctx, const double *base, const double *x, double *y,
+                             double *p_out, int transpose, int *passes, double *max_div);
+/* Largest max |D v| seen by asynchronous calls since the last query, and the
+ * number of such calls that needed more passes than the fixed count. Resets. */
+fvk_status fvk_simple_stats(fvk_ctx *ctx, double *max_div, int *n_unconverged);
+
+/* One Arnoldi step on A (or A^T): V holds j+1 orthonormal 4-field vectors
+ * with leading dimension ldv (doubles, >= n_total) and room for vector j+1.
+ * Computes w = A v_j, orthogonalises it against v_0..v_j by classical
+ * Gram-Schmidt with one re-orthogonalisation pass, stores v_{j+1} = w/|w| and
+ * writes h_col[0..j+1] (host): the new Hessenberg column with
+ * h_col[j+1] = |w|.  Returns FVK_EBREAKDOWN if |w| vanishes (then v_{j+1}
+ * is left unnormalised). */
+fvk_status arnoldi_step(fvk_ctx *ctx, const double *base, double *V, size_t ldv, int j,
+                        double *h_col, int transpose);
+
+/* ------------------------------------------------------- vector kernels */
+
+/* out[q] = <V_q, w> for q < m over n doubles (host out). */
+fvk_status fvk_multidot(fvk_ctx *ctx, const double *V, size_t ldv, int m, const double *w,
+                        size_t n, double *out);
+/* w <- alpha w + sum_q c[q] V_q (c host, m entries). */
+fvk_status fvk_multiaxpy(fvk_ctx *ctx, double *w, double alpha, const double *V, size_t ldv,
+                         int m, const double *c, size_t n);
+/* V[:, 0..k) <- V[:, 0..m) Q with Q host, column-major m x k (k <= m), in place
+ * (Krylov-Schur restart / Ritz vector assembly). */
+fvk_status fvk_basis_rotate(fvk_ctx *ctx, double *V, size_t ldv, int m, const double *Q, int k,
+                            size_t n);
+
+/* ----------------------------------------------------------------- Newton */
+
+typedef struct {
+    double tol;             /* stop when max |P F| < tol (default 1e-10)          */
+    int gmres_m;            /* GMRES restart length (100, Sec. 3.1)               */
+    int gmres_max_restarts; /* cap on GMRES(m) cycles per Newton step             */
+    double sat_ratio;       /* GMRES saturated when a cycle reduces |r| by less
+                               than this factor (0.9)                             */
+    int bicgstab_max_it;    /* BiCGstab(2) iterations after GMRES (5000)           */
+    double lin_tol;         /* relative residual target of the linear solve       */
+    int max_newton;         /* Newton iterations per call                          */
+} fvk_newton_opts;
+
+typedef struct {
+    double res_before, res_after;     /* max |P F| at entry / exit           */
+    int newton_its, gmres_cycles, bicgstab_its, krylov_vecs;
+    double lin_rel_res;               /* last linear relative residual       */
+    int lin_status;                   /* fvk_status of the last linear solve */
+} fvk_newton_report;
+
+void fvk_newton_defaults(fvk_newton_opts *opts);
+/* Newton iteration of Sec. 3.1 (steps 1-4) on `base` in place: b = P F;
+ * solve A delta = b by restarted GMRES(m) until converged or saturated, then
+ * BiCGstab(2) from the GMRES iterate; base <- base - delta; repeat up to
+ * max_newton times or until max |P F| < tol.  report may be NULL. */
+fvk_status newton_step(fvk_ctx *ctx, double *base, const fvk_newton_opts *opts,
+                       fvk_newton_report *report);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FVK_H */

@@ -88,6 +88,14 @@ class Oracle:
         v, _, _, _ = self.simple_project([x[0], x[1], x[2]])
         return torch.stack(v + [ext_T(self.grid, x[3], self.bc)])
 
+    def project_T(self, y):
+        """P^T y by reverse-mode differentiation of ``project`` (one pass)."""
+        x = torch.zeros(self.shape4, dtype=DT, requires_grad=True)
+        v, _, _, _ = self.simple_project([x[0], x[1], x[2]], passes=1)
+        Px = torch.stack(v + [ext_T(self.grid, x[3], self.bc)])
+        (g,) = torch.autograd.grad(Px, x, grad_outputs=y.to(DT))
+        return g.detach()
+
     # ---- the Krylov operator -----------------------------------------------
     def krylov_vec(self, base, x, passes=None, with_info=False):
         Jx = ops.jacvec(self.grid, self.prm, base, x)

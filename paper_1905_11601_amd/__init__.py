@@ -1,1 +1,229 @@
-"""Placeholder; replaced by the binding below."""
+"""fvk: Krylov-vector engine for the Newton / Arnoldi stability solver of
+buoyancy convection in a laterally heated cube (Gelfgat, arXiv:1905.11601) on
+AMD Instinct MI355X.
+
+Python binding over the C-ABI library ``libfvk.so`` (declared in
+``include/fvk.h``).  PyTorch supplies device memory and the stream; every
+step of the computation runs in the library's HIP kernels.  The names follow
+the C ABI: ``Ctx.fv_residual``, ``Ctx.fv_jacvec``, ``Ctx.simple_krylov_vec``,
+``Ctx.arnoldi_step``, ``Ctx.newton_step``.
+
+``paper_1905_11601_amd.inputs`` (seeded synthetic inputs) does not load the
+library; everything else does, and fails loudly if it is missing.
+"""
+import ctypes
+
+import numpy as np
+
+CC, AA = 0, 1
+UNIFORM, SINE, TANH = 0, 1, 2
+FP64, MIXED = 0, 1
+
+
+class FvkError(RuntimeError):
+    def __init__(self, status, msg):
+        from ._lib import STATUS
+        self.status = status
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Ctx:
+    """One grid / parameter set on one device stream (see fvk_create)."""
+
+    def __init__(self, nx, ny=None, nz=None, grid=TANH, s=1.5, span_bc=CC, Gr=1e6, Pr=0.71,
+                 prec=FP64, device="cuda:0", stream=None):
+        import torch
+        from . import _lib
+        self.lib = _lib.load()
+        self.torch = torch
+        ny = nx if ny is None else ny
+        nz = nx if nz is None else nz
+        self.n = (nx, ny, nz)
+        self.device = torch.device(device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = self.lib.fvk_create(ctypes.byref(h), nx, ny, nz, grid, float(s), span_bc,
+                                 float(Gr), float(Pr), prec, ctypes.c_void_p(stream.cuda_stream))
+        if st != 0:
+            raise FvkError(st, "fvk_create failed")
+        self.h = h
+        self.span_bc, self.grid_kind, self.s = span_bc, grid, s
+        self.Gr, self.Pr, self.prec = Gr, Pr, prec
+        F = ctypes.c_size_t()
+        N = ctypes.c_size_t()
+        self.lib.fvk_layout(h, None, ctypes.byref(F), ctypes.byref(N))
+        self.F, self.N = F.value, N.value
+        self.shape4 = (4, nz + 2, ny + 2, nx + 2)
+
+    # ---- housekeeping ------------------------------------------------------
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.fvk_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st):
+        if st != 0:
+            raise FvkError(st, self.lib.fvk_last_error(self.h).decode())
+
+    def _vec(self, t, name):
+        torch = self.torch
+        if not (isinstance(t, torch.Tensor) and t.dtype == torch.float64 and t.is_cuda
+                and t.is_contiguous() and t.numel() == self.N):
+            raise ValueError(f"{name}: need a contiguous float64 CUDA tensor of {self.N} elements")
+        return _ptr(t)
+
+    def empty(self):
+        return self.torch.empty(self.shape4, dtype=self.torch.float64, device=self.device)
+
+    def zeros(self):
+        return self.torch.zeros(self.shape4, dtype=self.torch.float64, device=self.device)
+
+    def set_params(self, Gr, Pr=None):
+        Pr = self.Pr if Pr is None else Pr
+        self._check(self.lib.fvk_set_params(self.h, float(Gr), float(Pr)))
+        self.Gr, self.Pr = Gr, Pr
+
+    def set_coeffs(self, nu, kappa, b):
+        self._check(self.lib.fvk_set_coeffs(self.h, float(nu), float(kappa), float(b)))
+
+    def set_precision(self, prec):
+        self._check(self.lib.fvk_set_precision(self.h, prec))
+        self.prec = prec
+
+    def set_simple(self, tol, max_passes):
+        self._check(self.lib.fvk_set_simple(self.h, float(tol), int(max_passes)))
+
+    def axis(self, a):
+        n = self.n[a]
+        f = np.zeros(n + 1)
+        c = np.zeros(n + 2)
+        w = np.zeros(n + 2)
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(self.lib.fvk_grid_axis(self.h, a, f.ctypes.data_as(dp), c.ctypes.data_as(dp),
+                                           w.ctypes.data_as(dp)))
+        return f, c, w
+
+    def coords(self):
+        ax = [self.axis(a) for a in range(3)]
+        return tuple(a[0] for a in ax), tuple(a[1] for a in ax), tuple(a[2] for a in ax)
+
+    # ---- operators (C-ABI names) ------------------------------------------
+    def fv_residual(self, base, out=None, project=False):
+        out = self.empty() if out is None else out
+        self._check(self.lib.fv_residual(self.h, self._vec(base, "base"), self._vec(out, "F"),
+                                         int(bool(project))))
+        return out
+
+    def fv_jacvec(self, base, x, out=None, transpose=False):
+        out = self.empty() if out is None else out
+        self._check(self.lib.fv_jacvec(self.h, self._vec(base, "base"), self._vec(x, "x"),
+                                       self._vec(out, "y"), int(bool(transpose))))
+        return out
+
+    def project(self, x, out=None, transpose=False):
+        out = self.empty() if out is None else out
+        self._check(self.lib.fvk_project(self.h, self._vec(x, "x"), self._vec(out, "y"),
+                                         int(bool(transpose))))
+        return out
+
+    def simple_krylov_vec(self, base, x, out=None, transpose=False, p_out=None, info=False):
+        out = self.empty() if out is None else out
+        pp = None
+        if p_out is not None:
+            if p_out.numel() != self.n[0] * self.n[1] * self.n[2] or p_out.dtype != self.torch.float64:
+                raise ValueError("p_out: need nx*ny*nz float64")
+            pp = _ptr(p_out)
+        if info:
+            k = ctypes.c_int()
+            d = ctypes.c_double()
+            st = self.lib.simple_krylov_vec(self.h, self._vec(base, "base"), self._vec(x, "x"),
+                                            self._vec(out, "y"), pp, int(bool(transpose)),
+                                            ctypes.byref(k), ctypes.byref(d))
+            self._check(st)
+            return out, k.value, d.value
+        self._check(self.lib.simple_krylov_vec(self.h, self._vec(base, "base"), self._vec(x, "x"),
+                                               self._vec(out, "y"), pp, int(bool(transpose)),
+                                               None, None))
+        return out
+
+    def simple_stats(self):
+        d = ctypes.c_double()
+        k = ctypes.c_int()
+        self._check(self.lib.fvk_simple_stats(self.h, ctypes.byref(d), ctypes.byref(k)))
+        return d.value, k.value
+
+    def arnoldi_step(self, base, V, j, transpose=False):
+        """V: (m+1, N) float64 CUDA tensor (rows are basis vectors)."""
+        if V.dim() != 2 or V.shape[1] != self.N or not V.is_contiguous() or j + 1 >= V.shape[0]:
+            raise ValueError("V must be a contiguous (m+1, N) tensor with room for vector j+1")
+        h = np.zeros(j + 2)
+        st = self.lib.arnoldi_step(self.h, self._vec(base, "base"), _ptr(V), V.shape[1], j,
+                                   h.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   int(bool(transpose)))
+        if st not in (0, 5):
+            self._check(st)
+        return h, st == 5
+
+    def multidot(self, V, m, w):
+        out = np.zeros(m)
+        self._check(self.lib.fvk_multidot(self.h, _ptr(V), V.shape[-1], m, _ptr(w), self.N,
+                                          out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def dot(self, x, y):
+        return float(self.multidot(x.reshape(1, -1), 1, y)[0])
+
+    def multiaxpy(self, w, alpha, V, c):
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        self._check(self.lib.fvk_multiaxpy(self.h, _ptr(w), float(alpha), _ptr(V), V.shape[-1],
+                                           len(c), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           self.N))
+
+    def basis_rotate(self, V, Q):
+        """V[:k] <- (V[:m]^T Q)^T with Q (m, k) real."""
+        Q = np.asfortranarray(Q, dtype=np.float64)
+        m, k = Q.shape
+        self._check(self.lib.fvk_basis_rotate(self.h, _ptr(V), V.shape[1], m,
+                                              Q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                              k, self.N))
+
+    def newton_step(self, base, **opts):
+        from ._lib import NewtonOpts, NewtonReport
+        o = NewtonOpts()
+        self.lib.fvk_newton_defaults(ctypes.byref(o))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        r = NewtonReport()
+        st = self.lib.newton_step(self.h, self._vec(base, "base"), ctypes.byref(o), ctypes.byref(r))
+        rep = {f: getattr(r, f) for f, _ in NewtonReport._fields_}
+        rep["status"] = st
+        return rep
+
+
+def tridiag_eig(diag, off):
+    """Host symmetric tridiagonal eigensolver of the library (eq. (15) set-up)."""
+    from . import _lib
+    lib = _lib.load()
+    diag = np.ascontiguousarray(diag, dtype=np.float64)
+    off = np.ascontiguousarray(off, dtype=np.float64)
+    n = len(diag)
+    lam = np.zeros(n)
+    Q = np.zeros((n, n))
+    dp = ctypes.POINTER(ctypes.c_double)
+    st = lib.fvk_tridiag_eig(n, diag.ctypes.data_as(dp), off.ctypes.data_as(dp),
+                             lam.ctypes.data_as(dp), Q.ctypes.data_as(dp))
+    if st != 0:
+        raise FvkError(st, "fvk_tridiag_eig failed")
+    return lam, Q

@@ -1,0 +1,535 @@
+// C-ABI entry points of the fvk library: context management, the operators of
+// the Krylov-vector path (paper Sec. 3.1) and the Arnoldi step around them.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "fvk_internal.h"
+
+using namespace fvk;
+
+#define HIPCHK(ctx, call)                                                              \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            (ctx)->err = std::string(#call) + ": " + hipGetErrorString(e_);            \
+            return FVK_EHIP;                                                           \
+        }                                                                              \
+    } while (0)
+
+#define CHECK_LAUNCH(ctx) HIPCHK(ctx, hipGetLastError())
+
+namespace {
+
+fvk_status fail(fvk_ctx *ctx, fvk_status st, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+template <typename T>
+fvk_status dalloc(fvk_ctx *ctx, T **p, size_t count) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+    if (e != hipSuccess) {
+        ctx->err = std::string("hipMalloc: ") + hipGetErrorString(e);
+        *p = nullptr;
+        return FVK_ENOMEM;
+    }
+    return FVK_OK;
+}
+
+void free_ws(fvk_ctx *ctx) {
+    Workspace &w = ctx->ws;
+    auto fr = [](void *p) {
+        if (p) (void)hipFree(p);
+    };
+    fr(w.geo);
+    fr(w.div);
+    fr(w.phi);
+    fr(w.tb0);
+    fr(w.tb1);
+    for (int a = 0; a < 3; ++a) {
+        fr(w.E[a]);
+        fr(w.Einv[a]);
+        fr(w.lam[a]);
+        fr(w.E32[a]);
+        fr(w.Einv32[a]);
+        fr(w.lam32[a]);
+    }
+    fr(w.vtmp);
+    fr(w.vtmp2);
+    fr(w.red);
+    fr(w.dev_scalars);
+    fr(w.dev_counters);
+    fr(w.coef_dev);
+    if (w.host_pinned) (void)hipHostFree(w.host_pinned);
+    w = Workspace();
+}
+
+void set_coefs_from_params(fvk_ctx *ctx) {
+    ctx->co.nu = 1.0 / std::sqrt(ctx->Gr);
+    ctx->co.kappa = ctx->co.nu / ctx->Pr;
+    ctx->co.b = 1.0;
+}
+
+size_t nvec(const fvk_ctx *ctx) { return size_t(4) * size_t(ctx->geo.F); }
+
+// Read `count` doubles from device memory into host `out` (synchronises).
+fvk_status read_back(fvk_ctx *ctx, const double *dev, double *out, size_t count) {
+    if (count > ctx->ws.host_pinned_len) return fail(ctx, FVK_EINVAL, "read_back too large");
+    HIPCHK(ctx, hipMemcpyAsync(ctx->ws.host_pinned, dev, count * sizeof(double),
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    std::memcpy(out, ctx->ws.host_pinned, count * sizeof(double));
+    return FVK_OK;
+}
+
+fvk_status write_coefs(fvk_ctx *ctx, const double *host, size_t count) {
+    if (count > ctx->ws.coef_len) return fail(ctx, FVK_EINVAL, "too many coefficients");
+    // stage through pinned memory so the copy is stream-ordered
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    std::memcpy(ctx->ws.host_pinned, host, count * sizeof(double));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->ws.coef_dev, ctx->ws.host_pinned, count * sizeof(double),
+                               hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return FVK_OK;
+}
+
+// ---- SIMPLE loop (Sec. 3.1, steps 1-3) ------------------------------------
+// vin: 3 velocity fields with zero wall entries (the momentum predictor);
+// vout: result (3 fields).  vin is clobbered when more than one pass runs.
+// sync: adaptive loop with a host check per pass; otherwise a fixed number of
+// passes and the divergence test is recorded on the device.
+fvk_status simple_forward(fvk_ctx *ctx, double *vin, double *vout, double *p_out, bool sync,
+                          int *passes_out, double *div_out) {
+    const Geo &g = ctx->geo;
+    Workspace &w = ctx->ws;
+    hipStream_t st = ctx->stream;
+    const bool fp32 = ctx->prec == FVK_MIXED;
+    const int fixed = fp32 ? ctx->mixed_passes : 1;
+    const int nred = correct_blocks(g);
+    if (p_out) launch_fill(p_out, 0.0, ctx->ncell, st);
+    launch_div(g, vin, w.div, st);
+    double *src = vin, *dst = vout;
+    int k = 0;
+    double dmax = 0.0;
+    while (true) {
+        tpf_solve(ctx, w.div, w.phi, fp32, st);
+        launch_correct_oop(g, src, dst, w.phi, p_out, w.div, w.red, st);
+        ++k;
+        const bool last_fixed = !sync && k >= fixed;
+        launch_max_reduce(w.red, nred, w.dev_scalars, last_fixed ? w.dev_scalars + 1 : nullptr,
+                          last_fixed ? w.dev_counters : nullptr, ctx->simple_tol, st);
+        CHECK_LAUNCH(ctx);
+        if (sync) {
+            fvk_status s = read_back(ctx, w.dev_scalars, &dmax, 1);
+            if (s != FVK_OK) return s;
+            if (dmax < ctx->simple_tol || k >= ctx->simple_cap) break;
+        } else if (k >= fixed) {
+            break;
+        }
+        std::swap(src, dst);
+    }
+    if (dst != vout) launch_copy(vout, dst, size_t(3) * g.F, st);
+    CHECK_LAUNCH(ctx);
+    if (passes_out) *passes_out = k;
+    if (div_out) *div_out = dmax;
+    if (sync && !(dmax < ctx->simple_tol))
+        return fail(ctx, FVK_ENOCONV, "SIMPLE loop hit its pass cap");
+    return FVK_OK;
+}
+
+// Transposed SIMPLE projection of a velocity part: z = P^T y = W P W^-1 y
+// (P is W-orthogonal, W = face control volumes), so the transposed loop is
+// the forward loop -- including its FP32 solves with FP64 refinement in mixed
+// mode -- between two diagonal scalings.  y is not modified; z may be any
+// 3-field buffer except ws.vtmp2.
+fvk_status simple_transpose(fvk_ctx *ctx, const double *y, double *z, bool sync,
+                            int *passes_out, double *div_out) {
+    const Geo &g = ctx->geo;
+    Workspace &w = ctx->ws;
+    launch_face_scale(g, y, w.vtmp2, 1, ctx->stream);
+    CHECK_LAUNCH(ctx);
+    fvk_status s = simple_forward(ctx, w.vtmp2, z, nullptr, sync, passes_out, div_out);
+    launch_face_scale(g, z, z, 0, ctx->stream);
+    CHECK_LAUNCH(ctx);
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+fvk_status fvk_create(fvk_ctx **out, int nx, int ny, int nz, int grid_kind, double s, int span_bc,
+                      double Gr, double Pr, int prec, void *hip_stream) {
+    if (!out) return FVK_EINVAL;
+    *out = nullptr;
+    if (nx < 2 || ny < 2 || nz < 2 || nx > 1024 || ny > 1024 || nz > 1024) return FVK_EINVAL;
+    if (grid_kind < 0 || grid_kind > 2 || (span_bc != 0 && span_bc != 1)) return FVK_EINVAL;
+    if (prec != FVK_FP64 && prec != FVK_MIXED) return FVK_EINVAL;
+    if (!(Gr > 0) || !(Pr > 0)) return FVK_EINVAL;
+    if (grid_kind == FVK_GRID_SINE && !(s >= 0 && s < 1.0 / (2.0 * M_PI))) return FVK_EINVAL;
+    if (grid_kind == FVK_GRID_TANH && !(s > 0)) return FVK_EINVAL;
+    fvk_ctx *ctx = new (std::nothrow) fvk_ctx();
+    if (!ctx) return FVK_ENOMEM;
+    ctx->n[0] = nx;
+    ctx->n[1] = ny;
+    ctx->n[2] = nz;
+    ctx->kind = grid_kind;
+    ctx->s = s;
+    ctx->bc = span_bc;
+    ctx->Gr = Gr;
+    ctx->Pr = Pr;
+    ctx->prec = prec;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    set_coefs_from_params(ctx);
+    for (int a = 0; a < 3; ++a) {
+        build_axis(ctx->ax[a], ctx->n[a], grid_kind, s);
+        neumann_eig(ctx->ax[a], ctx->eig[a]);
+    }
+    Geo &g = ctx->geo;
+    for (int a = 0; a < 3; ++a) {
+        g.n[a] = ctx->n[a];
+        g.np[a] = ctx->n[a] + 2;
+    }
+    g.s[0] = 1;
+    g.s[1] = g.np[0];
+    g.s[2] = long(g.np[0]) * g.np[1];
+    g.F = g.s[2] * g.np[2];
+    ctx->ncell = size_t(nx) * ny * nz;
+
+    fvk_status st = FVK_OK;
+    Workspace &w = ctx->ws;
+    // geometry: per axis 3 arrays of n+4 entries (offset by one)
+    std::vector<double> geo;
+    size_t off[3][3];
+    for (int a = 0; a < 3; ++a) {
+        const AxisHost &ah = ctx->ax[a];
+        const int n = ah.n;
+        std::vector<double> ih(n + 4, 0.0), id(n + 4, 0.0), ww(n + 4, 0.0);
+        for (int i = 1; i <= n; ++i) ih[i + 1] = 1.0 / ah.h[i];
+        for (int i = 0; i <= n; ++i) id[i + 1] = 1.0 / ah.d[i];
+        for (int i = 0; i <= n; ++i) ww[i + 1] = ah.w[i];
+        off[a][0] = geo.size();
+        geo.insert(geo.end(), ih.begin(), ih.end());
+        off[a][1] = geo.size();
+        geo.insert(geo.end(), id.begin(), id.end());
+        off[a][2] = geo.size();
+        geo.insert(geo.end(), ww.begin(), ww.end());
+    }
+    const size_t nc = ctx->ncell;
+    if ((st = dalloc(ctx, &w.geo, geo.size())) != FVK_OK) goto bad;
+    if ((st = dalloc(ctx, &w.div, nc)) != FVK_OK) goto bad;
+    if ((st = dalloc(ctx, &w.phi, nc)) != FVK_OK) goto bad;
+    if ((st = dalloc(ctx, reinterpret_cast<double **>(&w.tb0), nc)) != FVK_OK) goto bad;
+    if ((st = dalloc(ctx, reinterpret_cast<double **>(&w.tb1), nc)) != FVK_OK) goto bad;
+    if ((st = dalloc(ctx, &w.vtmp, nvec(ctx))) != FVK_OK) goto bad;
+    if ((st = dalloc(ctx, &w.vtmp2, nvec(ctx))) != FVK_OK) goto bad;
+    w.red_len = std::max<size_t>(size_t(correct_blocks(g)), size_t(multidot_blocks(nvec(ctx))) * 512);
+    if ((st = dalloc(ctx, &w.red, w.red_len)) != FVK_OK) goto bad;
+    if ((st = dalloc(ctx, &w.dev_scalars, 4096)) != FVK_OK) goto bad;
+    if ((st = dalloc(ctx, &w.dev_counters, 16)) != FVK_OK) goto bad;
+    w.coef_len = 65536;
+    if ((st = dalloc(ctx, &w.coef_dev, w.coef_len)) != FVK_OK) goto bad;
+    w.host_pinned_len = 65536;
+    if (hipHostMalloc(reinterpret_cast<void **>(&w.host_pinned),
+                      w.host_pinned_len * sizeof(double), 0) != hipSuccess) {
+        w.host_pinned = nullptr;
+        st = fail(ctx, FVK_ENOMEM, "hipHostMalloc failed");
+        goto bad;
+    }
+    for (int a = 0; a < 3; ++a) {
+        const int n = ctx->n[a];
+        const Eig1D &e = ctx->eig[a];
+        if ((st = dalloc(ctx, &w.E[a], size_t(n) * n)) != FVK_OK) goto bad;
+        if ((st = dalloc(ctx, &w.Einv[a], size_t(n) * n)) != FVK_OK) goto bad;
+        if ((st = dalloc(ctx, &w.lam[a], n)) != FVK_OK) goto bad;
+        if ((st = dalloc(ctx, &w.E32[a], size_t(n) * n)) != FVK_OK) goto bad;
+        if ((st = dalloc(ctx, &w.Einv32[a], size_t(n) * n)) != FVK_OK) goto bad;
+        if ((st = dalloc(ctx, &w.lam32[a], n)) != FVK_OK) goto bad;
+        std::vector<float> E32(e.E.begin(), e.E.end()), Ei32(e.Einv.begin(), e.Einv.end()),
+            l32(e.lam.begin(), e.lam.end());
+        if (hipMemcpy(w.E[a], e.E.data(), e.E.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(w.Einv[a], e.Einv.data(), e.Einv.size() * 8, hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(w.lam[a], e.lam.data(), e.lam.size() * 8, hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(w.E32[a], E32.data(), E32.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(w.Einv32[a], Ei32.data(), Ei32.size() * 4, hipMemcpyHostToDevice) !=
+                hipSuccess ||
+            hipMemcpy(w.lam32[a], l32.data(), l32.size() * 4, hipMemcpyHostToDevice) !=
+                hipSuccess) {
+            st = fail(ctx, FVK_EHIP, "eigenbasis upload failed");
+            goto bad;
+        }
+    }
+    if (hipMemcpy(w.geo, geo.data(), geo.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(w.dev_scalars, 0, 4096 * 8) != hipSuccess ||
+        hipMemset(w.dev_counters, 0, 16 * sizeof(int)) != hipSuccess) {
+        st = fail(ctx, FVK_EHIP, "geometry upload failed");
+        goto bad;
+    }
+    for (int a = 0; a < 3; ++a) {
+        g.ax[a].ih = w.geo + off[a][0] + 1;
+        g.ax[a].id = w.geo + off[a][1] + 1;
+        g.ax[a].w = w.geo + off[a][2] + 1;
+    }
+    *out = ctx;
+    return FVK_OK;
+bad:
+    free_ws(ctx);
+    delete ctx;
+    return st;
+}
+
+fvk_status fvk_destroy(fvk_ctx *ctx) {
+    if (!ctx) return FVK_EINVAL;
+    (void)hipStreamSynchronize(ctx->stream);
+    free_ws(ctx);
+    delete ctx;
+    return FVK_OK;
+}
+
+fvk_status fvk_set_stream(fvk_ctx *ctx, void *s) {
+    if (!ctx) return FVK_EINVAL;
+    ctx->stream = static_cast<hipStream_t>(s);
+    return FVK_OK;
+}
+
+fvk_status fvk_set_params(fvk_ctx *ctx, double Gr, double Pr) {
+    if (!ctx) return FVK_EINVAL;
+    if (!(Gr > 0) || !(Pr > 0)) return fail(ctx, FVK_EINVAL, "Gr and Pr must be positive");
+    ctx->Gr = Gr;
+    ctx->Pr = Pr;
+    set_coefs_from_params(ctx);
+    return FVK_OK;
+}
+
+fvk_status fvk_set_coeffs(fvk_ctx *ctx, double nu, double kappa, double b) {
+    if (!ctx) return FVK_EINVAL;
+    ctx->co.nu = nu;
+    ctx->co.kappa = kappa;
+    ctx->co.b = b;
+    return FVK_OK;
+}
+
+fvk_status fvk_set_precision(fvk_ctx *ctx, int prec) {
+    if (!ctx) return FVK_EINVAL;
+    if (prec != FVK_FP64 && prec != FVK_MIXED) return fail(ctx, FVK_EINVAL, "bad precision");
+    ctx->prec = prec;
+    return FVK_OK;
+}
+
+fvk_status fvk_set_simple(fvk_ctx *ctx, double tol, int max_passes) {
+    if (!ctx) return FVK_EINVAL;
+    if (!(tol > 0) || max_passes < 1 || max_passes > 100)
+        return fail(ctx, FVK_EINVAL, "bad SIMPLE settings");
+    ctx->simple_tol = tol;
+    ctx->simple_cap = max_passes;
+    return FVK_OK;
+}
+
+fvk_status fvk_layout(const fvk_ctx *ctx, size_t off[4], size_t *field_len, size_t *n_total) {
+    if (!ctx) return FVK_EINVAL;
+    const size_t F = size_t(ctx->geo.F);
+    if (off)
+        for (int f = 0; f < 4; ++f) off[f] = f * F;
+    if (field_len) *field_len = F;
+    if (n_total) *n_total = 4 * F;
+    return FVK_OK;
+}
+
+fvk_status fvk_grid_axis(const fvk_ctx *ctx, int axis, double *faces, double *centres,
+                         double *widths) {
+    if (!ctx || axis < 0 || axis > 2) return FVK_EINVAL;
+    const AxisHost &a = ctx->ax[axis];
+    if (faces) std::memcpy(faces, a.f.data(), a.f.size() * 8);
+    if (centres) std::memcpy(centres, a.c.data(), a.c.size() * 8);
+    if (widths) std::memcpy(widths, a.h.data(), a.h.size() * 8);
+    return FVK_OK;
+}
+
+const char *fvk_last_error(const fvk_ctx *ctx) {
+    if (!ctx) return "null context";
+    return ctx->err.c_str();
+}
+
+fvk_status fvk_tridiag_eig(int n, const double *diag, const double *off, double *lam, double *Q) {
+    if (n < 1 || !diag || !lam || !Q || (n > 1 && !off)) return FVK_EINVAL;
+    return tridiag_eig(n, diag, off, lam, Q) == 0 ? FVK_OK : FVK_ENOCONV;
+}
+
+fvk_status fv_residual(fvk_ctx *ctx, const double *base, double *F, int project) {
+    if (!ctx || !base || !F) return FVK_EINVAL;
+    const Geo &g = ctx->geo;
+    launch_residual(g, ctx->co, ctx->bc == FVK_SPAN_AA, base, F, ctx->stream);
+    CHECK_LAUNCH(ctx);
+    if (project) return fvk_project(ctx, F, F, 0);
+    return FVK_OK;
+}
+
+fvk_status fv_jacvec(fvk_ctx *ctx, const double *base, const double *x, double *y,
+                     int transpose) {
+    if (!ctx || !base || !x || !y) return FVK_EINVAL;
+    if (x == y) return fail(ctx, FVK_EINVAL, "x and y must not overlap");
+    const Geo &g = ctx->geo;
+    if (!transpose)
+        launch_jacvec(g, ctx->co, ctx->bc == FVK_SPAN_AA, 0, base, x, y, y + 3 * g.F, ctx->stream);
+    else
+        launch_jacvec_T(g, ctx->co, ctx->bc == FVK_SPAN_AA, 0, base, x, x + 3 * g.F, y,
+                        ctx->stream);
+    CHECK_LAUNCH(ctx);
+    return FVK_OK;
+}
+
+fvk_status fvk_project(fvk_ctx *ctx, const double *x, double *y, int transpose) {
+    if (!ctx || !x || !y) return FVK_EINVAL;
+    const Geo &g = ctx->geo;
+    Workspace &w = ctx->ws;
+    hipStream_t st = ctx->stream;
+    const long F = g.F;
+    const int aa = ctx->bc == FVK_SPAN_AA;
+    if (!transpose) {
+        launch_ext_T(g, aa, x + 3 * F, w.vtmp + 3 * F, st);
+        launch_zero_vel_walls(g, x, w.vtmp, st);
+        CHECK_LAUNCH(ctx);
+        int passes = 0;
+        double dmax = 0.0;
+        fvk_status s = simple_forward(ctx, w.vtmp, y, nullptr, true, &passes, &dmax);
+        launch_copy(y + 3 * F, w.vtmp + 3 * F, F, st);
+        CHECK_LAUNCH(ctx);
+        return s;
+    }
+    int passes = 0;
+    double dmax = 0.0;
+    fvk_status s = simple_transpose(ctx, x, w.vtmp, true, &passes, &dmax);
+    if (s != FVK_OK) return s;
+    launch_ext_T_T(g, aa, x + 3 * F, w.vtmp + 3 * F, st);
+    launch_copy(y, w.vtmp, size_t(4) * F, st);
+    CHECK_LAUNCH(ctx);
+    return FVK_OK;
+}
+
+fvk_status simple_krylov_vec(fvk_ctx *ctx, const double *base, const double *x, double *y,
+                             double *p_out, int transpose, int *passes, double *max_div) {
+    if (!ctx || !base || !x || !y) return FVK_EINVAL;
+    if (x == y) return fail(ctx, FVK_EINVAL, "x and y must not overlap");
+    const Geo &g = ctx->geo;
+    Workspace &w = ctx->ws;
+    hipStream_t st = ctx->stream;
+    const long F = g.F;
+    const int aa = ctx->bc == FVK_SPAN_AA;
+    if (!transpose) {
+        // momentum predictor + temperature RHS (eqs (11)-(12)), T part final
+        launch_jacvec(g, ctx->co, aa, 1, base, x, w.vtmp, y + 3 * F, st);
+        CHECK_LAUNCH(ctx);
+        const bool sync = passes || max_div;
+        int k = 0;
+        double dmax = 0.0;
+        fvk_status s = simple_forward(ctx, w.vtmp, y, p_out, sync, &k, &dmax);
+        if (passes) *passes = k;
+        if (max_div) *max_div = dmax;
+        return s;
+    }
+    const bool sync = passes || max_div;
+    int k = 0;
+    double dmax = 0.0;
+    fvk_status s = simple_transpose(ctx, x, w.vtmp, sync, &k, &dmax);
+    if (passes) *passes = k;
+    if (max_div) *max_div = dmax;
+    if (s != FVK_OK) return s;
+    launch_jacvec_T(g, ctx->co, aa, 1, base, w.vtmp, x + 3 * F, y, st);
+    CHECK_LAUNCH(ctx);
+    return FVK_OK;
+}
+
+fvk_status fvk_simple_stats(fvk_ctx *ctx, double *max_div, int *n_unconverged) {
+    if (!ctx) return FVK_EINVAL;
+    double tmp[2];
+    fvk_status s = read_back(ctx, ctx->ws.dev_scalars, tmp, 2);
+    if (s != FVK_OK) return s;
+    int cnt = 0;
+    HIPCHK(ctx, hipMemcpy(&cnt, ctx->ws.dev_counters, sizeof(int), hipMemcpyDeviceToHost));
+    if (max_div) *max_div = tmp[1];
+    if (n_unconverged) *n_unconverged = cnt;
+    launch_fill(ctx->ws.dev_scalars + 1, 0.0, 1, ctx->stream);
+    HIPCHK(ctx, hipMemsetAsync(ctx->ws.dev_counters, 0, sizeof(int), ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return FVK_OK;
+}
+
+fvk_status fvk_multidot(fvk_ctx *ctx, const double *V, size_t ldv, int m, const double *w,
+                        size_t n, double *out) {
+    if (!ctx || !V || !w || !out || m < 1 || m > 1024 || n == 0) return FVK_EINVAL;
+    const int nb = multidot_blocks(n);
+    if (size_t(nb) * m > ctx->ws.red_len) return fail(ctx, FVK_EINVAL, "too many vectors");
+    launch_multidot(V, ldv, m, w, n, ctx->ws.red, nb, ctx->stream);
+    launch_reduce_partials(ctx->ws.red, nb, m, ctx->ws.dev_scalars + 8, 0, ctx->stream);
+    CHECK_LAUNCH(ctx);
+    return read_back(ctx, ctx->ws.dev_scalars + 8, out, m);
+}
+
+fvk_status fvk_multiaxpy(fvk_ctx *ctx, double *w, double alpha, const double *V, size_t ldv,
+                         int m, const double *c, size_t n) {
+    if (!ctx || !w || !V || !c || m < 1 || n == 0) return FVK_EINVAL;
+    fvk_status s = write_coefs(ctx, c, m);
+    if (s != FVK_OK) return s;
+    launch_multiaxpy(w, alpha, 1.0, V, ldv, m, ctx->ws.coef_dev, n, ctx->stream);
+    CHECK_LAUNCH(ctx);
+    return FVK_OK;
+}
+
+fvk_status fvk_basis_rotate(fvk_ctx *ctx, double *V, size_t ldv, int m, const double *Q, int k,
+                            size_t n) {
+    if (!ctx || !V || !Q || m < 1 || k < 1 || k > m || m > 400 || n == 0) return FVK_EINVAL;
+    fvk_status s = write_coefs(ctx, Q, size_t(m) * k);
+    if (s != FVK_OK) return s;
+    launch_basis_rotate(V, ldv, m, ctx->ws.coef_dev, k, n, ctx->stream);
+    CHECK_LAUNCH(ctx);
+    return FVK_OK;
+}
+
+fvk_status arnoldi_step(fvk_ctx *ctx, const double *base, double *V, size_t ldv, int j,
+                        double *h_col, int transpose) {
+    if (!ctx || !base || !V || !h_col || j < 0 || j > 1000) return FVK_EINVAL;
+    const size_t n = nvec(ctx);
+    if (ldv < n) return fail(ctx, FVK_EINVAL, "ldv smaller than the vector length");
+    const int m = j + 1;
+    const int nb = multidot_blocks(n);
+    if (size_t(nb) * m > ctx->ws.red_len || m + 2 > 1000)
+        return fail(ctx, FVK_EINVAL, "Krylov dimension too large");
+    double *wv = V + size_t(j + 1) * ldv;
+    fvk_status s = simple_krylov_vec(ctx, base, V + size_t(j) * ldv, wv, nullptr, transpose,
+                                     nullptr, nullptr);
+    if (s != FVK_OK) return s;
+    hipStream_t st = ctx->stream;
+    double *h = ctx->ws.dev_scalars + 8;          // h[0..m)
+    double *hr = ctx->ws.dev_scalars + 8 + 1001;  // re-orthogonalisation coefficients
+    double *nrm = ctx->ws.dev_scalars + 4;
+    // classical Gram-Schmidt, then one full re-orthogonalisation pass (CGS2)
+    launch_multidot(V, ldv, m, wv, n, ctx->ws.red, nb, st);
+    launch_reduce_partials(ctx->ws.red, nb, m, h, 0, st);
+    launch_multiaxpy(wv, 1.0, -1.0, V, ldv, m, h, n, st);
+    launch_multidot(V, ldv, m, wv, n, ctx->ws.red, nb, st);
+    launch_reduce_partials(ctx->ws.red, nb, m, hr, 0, st);
+    launch_multiaxpy(wv, 1.0, -1.0, V, ldv, m, hr, n, st);
+    launch_axpby(h, 1.0, hr, 1.0, m, st);
+    launch_multidot(wv, ldv, 1, wv, n, ctx->ws.red, nb, st);
+    launch_reduce_partials(ctx->ws.red, nb, 1, nrm, 0, st);
+    launch_scale_inv_sqrt(wv, nrm, n, st);
+    CHECK_LAUNCH(ctx);
+    double nrm2 = 0.0;
+    s = read_back(ctx, h, h_col, m);
+    if (s != FVK_OK) return s;
+    s = read_back(ctx, nrm, &nrm2, 1);
+    if (s != FVK_OK) return s;
+    h_col[j + 1] = std::sqrt(nrm2);
+    if (!(nrm2 > 0.0) || !std::isfinite(nrm2))
+        return fail(ctx, FVK_EBREAKDOWN, "Arnoldi breakdown: |w| = 0 or not finite");
+    return FVK_OK;
+}
+
+}  // extern "C"

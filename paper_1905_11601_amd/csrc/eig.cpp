@@ -1,0 +1,152 @@
+// Host-side set-up: stretched staggered axes and the 1D eigendecompositions of
+// the Neumann pressure-correction operator (paper Sec. 3.1, eqs (14)-(15)).
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "fvk_internal.h"
+
+namespace fvk {
+
+static double face_map(double xi, int kind, double s) {
+    switch (kind) {
+        case FVK_GRID_SINE:  // eq. (22): x -> x - a sin(2 pi x)
+            return xi - s * std::sin(2.0 * M_PI * xi);
+        case FVK_GRID_TANH:
+            return 0.5 * (1.0 + std::tanh(s * (2.0 * xi - 1.0)) / std::tanh(s));
+        default:
+            return xi;
+    }
+}
+
+// Faces f[0..n] = map(i/n); centres at face midpoints plus the two wall nodes
+// c[0] = 0, c[n+1] = 1; widths h[i] = f[i]-f[i-1]; spacings d[i] = c[i+1]-c[i];
+// weights w[i] = (f[i]-c[i])/d[i] (w[0] = 0, w[n] = 1).
+void build_axis(AxisHost &a, int n, int kind, double s) {
+    a.n = n;
+    a.f.assign(n + 1, 0.0);
+    a.c.assign(n + 2, 0.0);
+    a.h.assign(n + 2, 0.0);
+    a.d.assign(n + 2, 0.0);
+    a.w.assign(n + 2, 0.0);
+    for (int i = 0; i <= n; ++i) a.f[i] = face_map(double(i) / n, kind, s);
+    a.f[0] = 0.0;
+    a.f[n] = 1.0;
+    for (int i = 1; i <= n; ++i) a.c[i] = 0.5 * (a.f[i - 1] + a.f[i]);
+    a.c[0] = 0.0;
+    a.c[n + 1] = 1.0;
+    for (int i = 1; i <= n; ++i) a.h[i] = a.f[i] - a.f[i - 1];
+    for (int i = 0; i <= n; ++i) a.d[i] = a.c[i + 1] - a.c[i];
+    for (int i = 0; i <= n; ++i) a.w[i] = (a.f[i] - a.c[i]) / a.d[i];
+    a.w[0] = 0.0;
+    a.w[n] = 1.0;
+}
+
+// Eigenvalues and orthonormal eigenvectors of the symmetric tridiagonal matrix
+// with diagonal diag[0..n) and off-diagonal off[0..n-1) (off[i] couples i and
+// i+1), by the implicit QL algorithm with Wilkinson-type shifts (Golub & Van
+// Loan, Sec. 8.3).  Q is n x n row-major; column q is the eigenvector of
+// lam[q].  Returns 0, or -1 if an eigenvalue needed more than 60 sweeps.
+int tridiag_eig(int n, const double *diag, const double *off, double *lam, double *Q) {
+    std::vector<double> d(diag, diag + n), e(n, 0.0);
+    for (int i = 0; i + 1 < n; ++i) e[i] = off[i];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) Q[i * n + j] = (i == j) ? 1.0 : 0.0;
+    const double eps = 2.220446049250313e-16;
+    for (int l = 0; l < n; ++l) {
+        int sweeps = 0;
+        while (true) {
+            int m = l;
+            for (; m < n - 1; ++m) {
+                double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
+                if (std::fabs(e[m]) <= eps * dd) break;
+            }
+            if (m == l) break;
+            if (++sweeps > 60) return -1;
+            // shift from the leading 2x2 block (eigenvalue closer to d[l])
+            double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
+            double r = std::hypot(g, 1.0);
+            g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
+            double sn = 1.0, cs = 1.0, p = 0.0;
+            int i = m - 1;
+            bool deflated = false;
+            for (; i >= l; --i) {
+                double f = sn * e[i], b = cs * e[i];
+                r = std::hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {  // exact split: undo the partial update
+                    d[i + 1] -= p;
+                    e[m] = 0.0;
+                    deflated = true;
+                    break;
+                }
+                sn = f / r;
+                cs = g / r;
+                g = d[i + 1] - p;
+                r = (d[i] - g) * sn + 2.0 * cs * b;
+                p = sn * r;
+                d[i + 1] = g + p;
+                g = cs * r - b;
+                for (int k = 0; k < n; ++k) {  // accumulate the plane rotation
+                    double qk1 = Q[k * n + i + 1], qk = Q[k * n + i];
+                    Q[k * n + i + 1] = sn * qk + cs * qk1;
+                    Q[k * n + i] = cs * qk - sn * qk1;
+                }
+            }
+            if (deflated) continue;
+            d[l] -= p;
+            e[l] = g;
+            e[m] = 0.0;
+        }
+    }
+    for (int i = 0; i < n; ++i) lam[i] = d[i];
+    return 0;
+}
+
+// D_aa = D_a G_a (Neumann): tridiagonal with V D_aa symmetric, V = diag(h).
+// S = V^1/2 D_aa V^-1/2 = Q diag(lam) Q^T gives E = V^-1/2 Q, E^-1 = Q^T V^1/2.
+// Eigenvalues sorted descending; the constant mode (lam = 0, E[:,0] = 1,
+// E^-1[0,:] = h) is set exactly.
+void neumann_eig(const AxisHost &a, Eig1D &e) {
+    const int n = a.n;
+    std::vector<double> diag(n), off(std::max(n - 1, 1), 0.0);
+    for (int i = 1; i <= n; ++i) {
+        double dg = 0.0;
+        if (i < n) dg -= 1.0 / (a.d[i] * a.h[i]);
+        if (i > 1) dg -= 1.0 / (a.d[i - 1] * a.h[i]);
+        diag[i - 1] = dg;
+        if (i < n) off[i - 1] = 1.0 / (a.d[i] * std::sqrt(a.h[i] * a.h[i + 1]));
+    }
+    std::vector<double> lam(n), Q(size_t(n) * n);
+    tridiag_eig(n, diag.data(), off.data(), lam.data(), Q.data());
+    std::vector<int> order(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::sort(order.begin(), order.end(), [&](int p, int q) { return lam[p] > lam[q]; });
+    e.n = n;
+    e.lam.assign(n, 0.0);
+    e.E.assign(size_t(n) * n, 0.0);
+    e.Einv.assign(size_t(n) * n, 0.0);
+    for (int q = 0; q < n; ++q) {
+        int src = order[q];
+        e.lam[q] = lam[src];
+        // fix the sign so the largest-magnitude component is positive
+        double big = 0.0;
+        for (int i = 0; i < n; ++i)
+            if (std::fabs(Q[i * n + src]) > std::fabs(big)) big = Q[i * n + src];
+        double sg = big < 0 ? -1.0 : 1.0;
+        for (int i = 0; i < n; ++i) {
+            double qv = sg * Q[i * n + src];
+            double sh = std::sqrt(a.h[i + 1]);
+            e.E[size_t(i) * n + q] = qv / sh;
+            e.Einv[size_t(q) * n + i] = qv * sh;
+        }
+    }
+    e.lam[0] = 0.0;
+    for (int i = 0; i < n; ++i) {
+        e.E[size_t(i) * n + 0] = 1.0;
+        e.Einv[size_t(0) * n + i] = a.h[i + 1];
+    }
+}
+
+}  // namespace fvk

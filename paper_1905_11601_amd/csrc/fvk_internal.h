@@ -1,0 +1,140 @@
+// Internal declarations of the fvk library (context, device geometry, kernel
+// launchers).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fvk.h"
+
+namespace fvk {
+
+// Per-axis coefficient arrays on the device.  Each array has n+4 entries and
+// the pointer is offset by one, so indices -1 .. n+2 are addressable; entries
+// outside an array's valid range hold 0 (so reciprocals vanish there).
+//   ih[i] = 1/h[i]           (i = 1..n)      cell widths
+//   id[i] = 1/d[i]           (i = 0..n)      centre spacings
+//   w[i]  = (f[i]-c[i])/d[i] (i = 0..n)      face interpolation weight
+struct AxisDev {
+    const double *ih, *id, *w;
+};
+
+struct Geo {
+    int n[3];       // cells per axis
+    int np[3];      // n + 2 (stored extent per axis)
+    long s[3];      // strides: 1, np[0], np[0]*np[1]
+    long F;         // field length
+    AxisDev ax[3];
+};
+
+struct Coefs {
+    double nu, kappa, b;
+};
+
+// Host-side description of one axis (natural indexing, see fvk.h).
+struct AxisHost {
+    int n = 0;
+    std::vector<double> f, c, h, d, w;
+};
+
+// One-axis eigendecomposition of the Neumann operator D_aa = E diag(lam) E^-1
+// (row-major n x n matrices), lam[0] = 0 is the constant mode.
+struct Eig1D {
+    int n = 0;
+    std::vector<double> lam, E, Einv;
+};
+
+struct Workspace {
+    double *geo = nullptr;          // packed AxisDev arrays
+    double *div = nullptr;          // n cells (compact), also r/V in transposed passes
+    double *phi = nullptr;          // n cells (compact) FP64 Poisson solution
+    void *tb0 = nullptr, *tb1 = nullptr;   // transform ping-pong buffers (FP64 sized)
+    double *E[3] = {}, *Einv[3] = {}, *lam[3] = {};
+    float *E32[3] = {}, *Einv32[3] = {}, *lam32[3] = {};
+    double *vtmp = nullptr;         // 4-field scratch vector
+    double *vtmp2 = nullptr;        // 4-field scratch vector (transposed SIMPLE)
+    double *coef_dev = nullptr;     // small coefficient arrays copied from the host
+    size_t coef_len = 0;
+    double *red = nullptr;          // reduction scratch (partials)
+    size_t red_len = 0;
+    double *dev_scalars = nullptr;  // [0] max div of last pass, [1] running max (async)
+    int *dev_counters = nullptr;    // [0] async calls above tolerance
+    double *host_pinned = nullptr;  // pinned host staging for small reads
+    size_t host_pinned_len = 0;
+};
+
+}  // namespace fvk
+
+struct fvk_ctx {
+    int n[3] = {0, 0, 0};
+    int kind = 0;
+    double s = 0.0;
+    int bc = 0;
+    double Gr = 0.0, Pr = 0.0;
+    fvk::Coefs co{0.0, 0.0, 1.0};
+    int prec = 0;
+    hipStream_t stream = nullptr;
+    double simple_tol = 1e-9;
+    int simple_cap = 10;
+    int mixed_passes = 2;           // fixed pass count of asynchronous mixed calls
+    fvk::AxisHost ax[3];
+    fvk::Eig1D eig[3];
+    fvk::Geo geo{};
+    fvk::Workspace ws;
+    size_t ncell = 0;
+    std::string err;
+};
+
+namespace fvk {
+
+// ---- host utilities (eig.cpp)
+void build_axis(AxisHost &a, int n, int kind, double s);
+void neumann_eig(const AxisHost &a, Eig1D &e);
+int tridiag_eig(int n, const double *diag, const double *off, double *lam, double *Q);
+
+// ---- stencil kernels (kernels_stencil.hip); all enqueue on `st`
+// y_v (3 fields) / y_T (1 field) = J x; ext != 0 applies Ext_T to the T part
+void launch_jacvec(const Geo &g, Coefs c, int span_aa, int ext, const double *base,
+                   const double *x, double *yv, double *yT, hipStream_t st);
+void launch_jacvec_T(const Geo &g, Coefs c, int span_aa, int fold_ext, const double *base,
+                     const double *yvel, const double *yT, double *x, hipStream_t st);
+void launch_residual(const Geo &g, Coefs c, int span_aa, const double *base, double *F,
+                     hipStream_t st);
+void launch_div(const Geo &g, const double *v, double *div, hipStream_t st);
+void launch_correct_oop(const Geo &g, const double *vin, double *vout, const double *phi,
+                        double *p_out, double *div_out, double *red, hipStream_t st);
+int correct_blocks(const Geo &g);
+// interior velocity faces scaled by W = d_A h_B h_C (inverse: by 1/W), rest 0
+void launch_face_scale(const Geo &g, const double *src, double *dst, int inverse,
+                       hipStream_t st);
+void launch_ext_T(const Geo &g, int span_aa, const double *src, double *dst, hipStream_t st);
+void launch_ext_T_T(const Geo &g, int span_aa, const double *src, double *dst, hipStream_t st);
+void launch_zero_vel_walls(const Geo &g, const double *src, double *dst, hipStream_t st);
+
+// ---- TPF (kernels_tpf.hip)
+void tpf_solve(fvk_ctx *ctx, const double *b, double *phi, bool fp32, hipStream_t st);
+
+// ---- BLAS-like kernels (kernels_blas.hip)
+int multidot_blocks(size_t n);
+void launch_multidot(const double *V, size_t ldv, int m, const double *w, size_t n,
+                     double *partials, int nblk, hipStream_t st);
+void launch_reduce_partials(const double *partials, int nblk, int m, double *out, int accumulate,
+                            hipStream_t st);
+void launch_multiaxpy(double *w, double alpha, double beta, const double *V, size_t ldv, int m,
+                      const double *c_dev, size_t n, hipStream_t st);
+void launch_basis_rotate(double *V, size_t ldv, int m, const double *Q_dev, int k, size_t n,
+                         hipStream_t st);
+void launch_max_reduce(const double *partials, int nblk, double *out, double *running,
+                       int *count_over, double tol, hipStream_t st);
+void launch_absmax(const double *x, size_t n, double *partials, int nblk, hipStream_t st);
+void launch_scale_inv_sqrt(double *w, const double *nrm2, size_t n, hipStream_t st);
+void launch_axpby(double *y, double a, const double *x, double b, size_t n, hipStream_t st);
+void launch_fill(double *y, double v, size_t n, hipStream_t st);
+void launch_copy(double *dst, const double *src, size_t n, hipStream_t st);
+void launch_scale(double *w, double alpha, size_t n, hipStream_t st);
+
+}  // namespace fvk

@@ -1,0 +1,540 @@
+// Finite-volume stencil kernels on the staggered grid with stored wall nodes
+// (paper Sec. 3.1: residual of eqs (1)-(2), Jacobian of eqs (8)-(9), the
+// divergence / gradient pair of the SIMPLE pass, the temperature projection of
+// eq. (21) in its boundary-local form) and their Euclidean transposes.
+//
+// Field layout: (nz+2, ny+2, nx+2), x fastest.  A 4-field vector holds
+// u (x-faces), v (y-faces), w (z-faces), T (centres) back to back.  Rows of the
+// momentum equation for component A are the interior A-faces
+// (1 <= i_A <= n_A - 1, 1 <= i_B <= n_B for B != A); rows of the energy
+// equation are the interior cells.  Forward kernels write every stored entry
+// (0 where the operator has no row).
+#include "fvk_internal.h"
+
+namespace fvk {
+
+namespace {
+
+constexpr int BX = 64, BY = 4;
+
+__device__ __forceinline__ bool face_row(const Geo &g, int A, int i, int j, int k) {
+    const int idx[3] = {i, j, k};
+#pragma unroll
+    for (int B = 0; B < 3; ++B) {
+        const int hi = (B == A) ? g.n[B] - 1 : g.n[B];
+        if (idx[B] < 1 || idx[B] > hi) return false;
+    }
+    return true;
+}
+
+__device__ __forceinline__ bool cell_row(const Geo &g, int i, int j, int k) {
+    return i >= 1 && i <= g.n[0] && j >= 1 && j <= g.n[1] && k >= 1 && k <= g.n[2];
+}
+
+__device__ __forceinline__ bool in_box(const Geo &g, int i, int j, int k) {
+    return i >= 0 && i < g.np[0] && j >= 0 && j < g.np[1] && k >= 0 && k < g.np[2];
+}
+
+__device__ __forceinline__ long pos(const Geo &g, int i, int j, int k) {
+    return (long(k) * g.np[1] + j) * g.np[0] + i;
+}
+
+// ---------------------------------------------------------------- forward
+
+// Momentum row of component A at stored position p (an interior A-face).
+// Returns nu*Lap(X_A) - [N_A(a1, b1_A) + N_A(a2, b2_A)] * adv_scale
+//         + bcoef * T interpolated to the z-face (A == 2).
+// N_A(a, b): conservative flux form of (a.grad) b_A on the A-face control
+// volume: normal fluxes at the two adjacent cell centres (midpoint averages),
+// tangential fluxes at the edges (a_B interpolated along A with w_A, b_A
+// interpolated along B with w_B).
+template <int A>
+__device__ __forceinline__ double mom_row(const Geo &g, const int *idx, long p,
+                                          const double *const *a1, const double *const *b1,
+                                          const double *const *a2, const double *const *b2,
+                                          double adv_scale, const double *X, double nu,
+                                          const double *T, double bcoef) {
+    const long sA = g.s[A];
+    const int ia = idx[A];
+    const AxisDev &aA = g.ax[A];
+    const double idA = aA.id[ia];
+    double adv, lap;
+    {
+        const double A1p = 0.5 * (a1[A][p] + a1[A][p + sA]), A1m = 0.5 * (a1[A][p - sA] + a1[A][p]);
+        const double B1p = 0.5 * (b1[A][p] + b1[A][p + sA]), B1m = 0.5 * (b1[A][p - sA] + b1[A][p]);
+        const double A2p = 0.5 * (a2[A][p] + a2[A][p + sA]), A2m = 0.5 * (a2[A][p - sA] + a2[A][p]);
+        const double B2p = 0.5 * (b2[A][p] + b2[A][p + sA]), B2m = 0.5 * (b2[A][p - sA] + b2[A][p]);
+        adv = (A1p * B1p - A1m * B1m + A2p * B2p - A2m * B2m) * idA;
+        lap = ((X[p + sA] - X[p]) * aA.ih[ia + 1] - (X[p] - X[p - sA]) * aA.ih[ia]) * idA;
+    }
+    const double wa = aA.w[ia];
+#pragma unroll
+    for (int t = 1; t <= 2; ++t) {
+        const int Bt = (A + t) % 3;
+        const long sB = g.s[Bt];
+        const int jb = idx[Bt];
+        const AxisDev &aB = g.ax[Bt];
+        const double wbp = aB.w[jb], wbm = aB.w[jb - 1];
+        // transporting component Bt at the edges (A-face, Bt-face jb / jb-1)
+        const double t1p = (1.0 - wa) * a1[Bt][p] + wa * a1[Bt][p + sA];
+        const double t1m = (1.0 - wa) * a1[Bt][p - sB] + wa * a1[Bt][p + sA - sB];
+        const double t2p = (1.0 - wa) * a2[Bt][p] + wa * a2[Bt][p + sA];
+        const double t2m = (1.0 - wa) * a2[Bt][p - sB] + wa * a2[Bt][p + sA - sB];
+        // transported component A at the same edges
+        const double s1p = (1.0 - wbp) * b1[A][p] + wbp * b1[A][p + sB];
+        const double s1m = (1.0 - wbm) * b1[A][p - sB] + wbm * b1[A][p];
+        const double s2p = (1.0 - wbp) * b2[A][p] + wbp * b2[A][p + sB];
+        const double s2m = (1.0 - wbm) * b2[A][p - sB] + wbm * b2[A][p];
+        adv += (t1p * s1p - t1m * s1m + t2p * s2p - t2m * s2m) * aB.ih[jb];
+        lap += ((X[p + sB] - X[p]) * aB.id[jb] - (X[p] - X[p - sB]) * aB.id[jb - 1]) * aB.ih[jb];
+    }
+    double r = nu * lap - adv_scale * adv;
+    if (A == 2) r += bcoef * ((1.0 - wa) * T[p] + wa * T[p + sA]);
+    return r;
+}
+
+// Energy row at an interior cell p: kappa Lap(Tl) - N_T(a1, b1) - N_T(a2, b2);
+// N_T(a, b) = sum_A [a_A b_face]_{face-}^{face+} / h_A.  a2 may be null.
+__device__ __forceinline__ double energy_row(const Geo &g, const int *idx, long p,
+                                             const double *const *a1, const double *b1,
+                                             const double *const *a2, const double *b2,
+                                             const double *Tl, double kappa) {
+    double adv = 0.0, lap = 0.0;
+#pragma unroll
+    for (int A = 0; A < 3; ++A) {
+        const long sA = g.s[A];
+        const int ia = idx[A];
+        const AxisDev &aA = g.ax[A];
+        const double wp = aA.w[ia], wm = aA.w[ia - 1], ih = aA.ih[ia];
+        const double f1p = (1.0 - wp) * b1[p] + wp * b1[p + sA];
+        const double f1m = (1.0 - wm) * b1[p - sA] + wm * b1[p];
+        double a = a1[A][p] * f1p - a1[A][p - sA] * f1m;
+        if (a2) {
+            const double f2p = (1.0 - wp) * b2[p] + wp * b2[p + sA];
+            const double f2m = (1.0 - wm) * b2[p - sA] + wm * b2[p];
+            a += a2[A][p] * f2p - a2[A][p - sA] * f2m;
+        }
+        adv += a * ih;
+        lap += ((Tl[p + sA] - Tl[p]) * aA.id[ia] - (Tl[p] - Tl[p - sA]) * aA.id[ia - 1]) * ih;
+    }
+    return kappa * lap - adv;
+}
+
+// y = J(base) x on every stored entry (velocity part to yv, T part to yT).
+// With span_aa set (insulated y-walls and the extension requested) the
+// temperature part is returned extended by the homogeneous BCs: insulated
+// y-wall nodes = adjacent interior value, i.e. Ext_T (J x)_T; Dirichlet wall
+// nodes are 0 either way.
+// mode 0: Jacobian; mode 1: residual F(base) (x ignored).
+template <int MODE>
+__global__ __launch_bounds__(BX *BY) void k_jac(Geo g, Coefs c, int span_aa,
+                                                const double *__restrict__ base,
+                                                const double *__restrict__ x,
+                                                double *__restrict__ yv,
+                                                double *__restrict__ yT) {
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.np[0] || j >= g.np[1] || k >= g.np[2]) return;
+    const long F = g.F;
+    const long p = pos(g, i, j, k);
+    const int idx[3] = {i, j, k};
+    const double *U[3] = {base, base + F, base + 2 * F};
+    const double *Th = base + 3 * F;
+    const double *X[3] = {x, x + F, x + 2 * F};
+    const double *XT = x + 3 * F;
+    double out[3];
+#pragma unroll
+    for (int A = 0; A < 3; ++A) out[A] = 0.0;
+    if (face_row(g, 0, i, j, k))
+        out[0] = (MODE == 0) ? mom_row<0>(g, idx, p, U, X, X, U, 1.0, X[0], c.nu, XT, c.b)
+                             : mom_row<0>(g, idx, p, U, U, U, U, 0.5, U[0], c.nu, Th, c.b);
+    if (face_row(g, 1, i, j, k))
+        out[1] = (MODE == 0) ? mom_row<1>(g, idx, p, U, X, X, U, 1.0, X[1], c.nu, XT, c.b)
+                             : mom_row<1>(g, idx, p, U, U, U, U, 0.5, U[1], c.nu, Th, c.b);
+    if (face_row(g, 2, i, j, k))
+        out[2] = (MODE == 0) ? mom_row<2>(g, idx, p, U, X, X, U, 1.0, X[2], c.nu, XT, c.b)
+                             : mom_row<2>(g, idx, p, U, U, U, U, 0.5, U[2], c.nu, Th, c.b);
+    yv[p] = out[0];
+    yv[p + F] = out[1];
+    yv[p + 2 * F] = out[2];
+    // temperature (row or insulated-wall copy of the adjacent row)
+    double t = 0.0;
+    int jr = j;
+    bool have = cell_row(g, i, j, k);
+    if (!have && span_aa && i >= 1 && i <= g.n[0] && k >= 1 && k <= g.n[2]) {
+        if (j == 0) { jr = 1; have = true; }
+        if (j == g.n[1] + 1) { jr = g.n[1]; have = true; }
+    }
+    if (have) {
+        const int idr[3] = {i, jr, k};
+        const long pr = pos(g, i, jr, k);
+        t = (MODE == 0) ? energy_row(g, idr, pr, U, XT, X, Th, XT, c.kappa)
+                        : energy_row(g, idr, pr, U, Th, nullptr, nullptr, Th, c.kappa);
+    }
+    yT[p] = t;
+}
+
+// ---------------------------------------------------------------- transpose
+
+__device__ __forceinline__ double ld(const Geo &g, const double *f, int i, int j, int k) {
+    return in_box(g, i, j, k) ? f[pos(g, i, j, k)] : 0.0;
+}
+
+// Y restricted to the rows of the momentum equation of component A.
+__device__ __forceinline__ double yv(const Geo &g, int A, const double *Y, int i, int j, int k) {
+    return face_row(g, A, i, j, k) ? Y[pos(g, i, j, k)] : 0.0;
+}
+
+// Y restricted to energy rows; with fold, the insulated-wall entries are added
+// to their neighbours (transpose of the boundary-local extension Ext_T).
+__device__ __forceinline__ double yt(const Geo &g, int fold, const double *Y, int i, int j, int k) {
+    if (!cell_row(g, i, j, k)) return 0.0;
+    const long p = pos(g, i, j, k);
+    double r = Y[p];
+    if (fold) {
+        if (j == 1) r += Y[p - g.s[1]];
+        if (j == g.n[1]) r += Y[p + g.s[1]];
+    }
+    return r;
+}
+
+// Transposed momentum-variable output for component A at stored position
+// (i, j, k): collects every row in which x_A at this position appears, using
+// the flux-adjoint form g = (row differences of Y) of each flux.
+template <int A>
+__device__ double jacT_vel(const Geo &g, Coefs c, const int *idx, const double *const *U,
+                           const double *Th, const double *const *Yv, const double *YT,
+                           int fold) {
+    const int i = idx[0], j = idx[1], k = idx[2];
+    const AxisDev &aA = g.ax[A];
+    const int ia = idx[A];
+    int eA[3] = {0, 0, 0};
+    eA[A] = 1;
+    const double yc = yv(g, A, Yv[A], i, j, k);
+    const double ym = yv(g, A, Yv[A], i - eA[0], j - eA[1], k - eA[2]);
+    const double yp = yv(g, A, Yv[A], i + eA[0], j + eA[1], k + eA[2]);
+    // viscous, normal direction
+    double lapT = -(aA.ih[ia + 1] + aA.ih[ia]) * aA.id[ia] * yc + aA.ih[ia] * aA.id[ia - 1] * ym +
+                  aA.ih[ia + 1] * aA.id[ia + 1] * yp;
+    // advection, normal direction: - [Ubar(c=ia) gn(ia) + Ubar(c=ia+1) gn(ia+1)]
+    const double uc = ld(g, U[A], i, j, k);
+    const double um = ld(g, U[A], i - eA[0], j - eA[1], k - eA[2]);
+    const double up = ld(g, U[A], i + eA[0], j + eA[1], k + eA[2]);
+    double advT = 0.5 * (um + uc) * (ym * aA.id[ia - 1] - yc * aA.id[ia]) +
+                  0.5 * (uc + up) * (yc * aA.id[ia] - yp * aA.id[ia + 1]);
+    const double wa = aA.w[ia];
+#pragma unroll
+    for (int t = 1; t <= 2; ++t) {
+        const int Bt = (A + t) % 3;
+        const AxisDev &aB = g.ax[Bt];
+        const int jb = idx[Bt];
+        int eB[3] = {0, 0, 0};
+        eB[Bt] = 1;
+        const double ymB = yv(g, A, Yv[A], i - eB[0], j - eB[1], k - eB[2]);
+        const double ypB = yv(g, A, Yv[A], i + eB[0], j + eB[1], k + eB[2]);
+        lapT += -(aB.id[jb] + aB.id[jb - 1]) * aB.ih[jb] * yc + aB.id[jb - 1] * aB.ih[jb - 1] * ymB +
+                aB.id[jb] * aB.ih[jb + 1] * ypB;
+        // U_Bt interpolated along A to this A-face, at Bt-faces jb and jb-1
+        const double ut_p = (1.0 - wa) * ld(g, U[Bt], i, j, k) +
+                            wa * ld(g, U[Bt], i + eA[0], j + eA[1], k + eA[2]);
+        const double ut_m = (1.0 - wa) * ld(g, U[Bt], i - eB[0], j - eB[1], k - eB[2]) +
+                            wa * ld(g, U[Bt], i + eA[0] - eB[0], j + eA[1] - eB[1], k + eA[2] - eB[2]);
+        // (3) x_A transported in the A-rows along Bt
+        const double gt_p = yc * aB.ih[jb] - ypB * aB.ih[jb + 1];
+        const double gt_m = ymB * aB.ih[jb - 1] - yc * aB.ih[jb];
+        advT += ut_p * (1.0 - aB.w[jb]) * gt_p + ut_m * aB.w[jb - 1] * gt_m;
+        // (4) x_A transporting U_Bt in the Bt-rows along A
+        const double ybc = yv(g, Bt, Yv[Bt], i, j, k);
+        const double ybA = yv(g, Bt, Yv[Bt], i + eA[0], j + eA[1], k + eA[2]);
+        const double ybm = yv(g, Bt, Yv[Bt], i - eB[0], j - eB[1], k - eB[2]);
+        const double ybmA = yv(g, Bt, Yv[Bt], i - eB[0] + eA[0], j - eB[1] + eA[1], k - eB[2] + eA[2]);
+        const double gq_p = ybc * aA.ih[ia] - ybA * aA.ih[ia + 1];
+        const double gq_m = ybm * aA.ih[ia] - ybmA * aA.ih[ia + 1];
+        advT += (1.0 - aB.w[jb]) * ut_p * gq_p + aB.w[jb - 1] * ut_m * gq_m;
+    }
+    // (5) x_A transporting Theta in the energy rows
+    const double thf = (1.0 - wa) * ld(g, Th, i, j, k) + wa * ld(g, Th, i + eA[0], j + eA[1], k + eA[2]);
+    const double tc = yt(g, fold, YT, i, j, k);
+    const double tp = yt(g, fold, YT, i + eA[0], j + eA[1], k + eA[2]);
+    advT += thf * (tc * aA.ih[ia] - tp * aA.ih[ia + 1]);
+    return c.nu * lapT - advT;
+}
+
+__device__ double jacT_temp(const Geo &g, Coefs c, const int *idx, const double *const *U,
+                            const double *Yw, const double *YT, int fold) {
+    const int i = idx[0], j = idx[1], k = idx[2];
+    const double tc = yt(g, fold, YT, i, j, k);
+    double lapT = 0.0, advT = 0.0;
+#pragma unroll
+    for (int A = 0; A < 3; ++A) {
+        const AxisDev &aA = g.ax[A];
+        const int ia = idx[A];
+        int e[3] = {0, 0, 0};
+        e[A] = 1;
+        const double tm = yt(g, fold, YT, i - e[0], j - e[1], k - e[2]);
+        const double tp = yt(g, fold, YT, i + e[0], j + e[1], k + e[2]);
+        lapT += -(aA.id[ia] + aA.id[ia - 1]) * aA.ih[ia] * tc + aA.id[ia - 1] * aA.ih[ia - 1] * tm +
+                aA.id[ia] * aA.ih[ia + 1] * tp;
+        const double uq = ld(g, U[A], i, j, k);
+        const double uqm = ld(g, U[A], i - e[0], j - e[1], k - e[2]);
+        const double g_p = tc * aA.ih[ia] - tp * aA.ih[ia + 1];
+        const double g_m = tm * aA.ih[ia - 1] - tc * aA.ih[ia];
+        advT += uq * (1.0 - aA.w[ia]) * g_p + uqm * aA.w[ia - 1] * g_m;
+    }
+    // buoyancy: the w-rows read T at the z-centres k and k+1
+    const AxisDev &az = g.ax[2];
+    const double buo = (1.0 - az.w[k]) * yv(g, 2, Yw, i, j, k) + az.w[k - 1] * yv(g, 2, Yw, i, j, k - 1);
+    return c.kappa * lapT - advT + c.b * buo;
+}
+
+__global__ __launch_bounds__(BX *BY) void k_jacT(Geo g, Coefs c, int fold,
+                                                 const double *__restrict__ base,
+                                                 const double *__restrict__ yvel,
+                                                 const double *__restrict__ yT,
+                                                 double *__restrict__ x) {
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.np[0] || j >= g.np[1] || k >= g.np[2]) return;
+    const long F = g.F;
+    const long p = pos(g, i, j, k);
+    const int idx[3] = {i, j, k};
+    const double *U[3] = {base, base + F, base + 2 * F};
+    const double *Th = base + 3 * F;
+    const double *Y[3] = {yvel, yvel + F, yvel + 2 * F};
+    x[p] = jacT_vel<0>(g, c, idx, U, Th, Y, yT, fold);
+    x[p + F] = jacT_vel<1>(g, c, idx, U, Th, Y, yT, fold);
+    x[p + 2 * F] = jacT_vel<2>(g, c, idx, U, Th, Y, yT, fold);
+    x[p + 3 * F] = jacT_temp(g, c, idx, U, Y[2], yT, fold);
+}
+
+// ---------------------------------------------------------------- SIMPLE pieces
+
+__device__ __forceinline__ long cidx(const Geo &g, int i, int j, int k) {
+    return (long(k - 1) * g.n[1] + (j - 1)) * g.n[0] + (i - 1);
+}
+
+// D v at interior cells (compact output).
+__global__ __launch_bounds__(BX *BY) void k_div(Geo g, const double *__restrict__ v,
+                                                double *__restrict__ dv) {
+    const int i = blockIdx.x * BX + threadIdx.x + 1;
+    const int j = blockIdx.y * BY + threadIdx.y + 1;
+    const int k = blockIdx.z + 1;
+    if (i > g.n[0] || j > g.n[1] || k > g.n[2]) return;
+    const long p = pos(g, i, j, k);
+    const int idx[3] = {i, j, k};
+    double s = 0.0;
+#pragma unroll
+    for (int A = 0; A < 3; ++A)
+        s += (v[A * g.F + p] - v[A * g.F + p - g.s[A]]) * g.ax[A].ih[idx[A]];
+    dv[cidx(g, i, j, k)] = s;
+}
+
+__device__ __forceinline__ double block_max(double v, double *sh) {
+    // wavefront reduction, then across the waves of the block
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    const int t = threadIdx.y * blockDim.x + threadIdx.x;
+    const int lane = t & 63, wv = t >> 6;
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    const int nw = (blockDim.x * blockDim.y + 63) / 64;
+    double r = 0.0;
+    if (t == 0) {
+        for (int q = 0; q < nw; ++q) r = fmax(r, sh[q]);
+    }
+    return r;
+}
+
+// v_out = v_in - G phi on interior faces (walls keep v_in), p_out += phi,
+// div_out = D v_out, block maxima of |D v_out| to red[block].
+// Each thread owns the + faces of its cell; the - faces are recomputed from
+// v_in so the kernel is race-free with v_out != v_in.
+__global__ __launch_bounds__(BX *BY) void k_correct(Geo g, const double *__restrict__ vin,
+                                                    const double *__restrict__ phi,
+                                                    double *__restrict__ vout,
+                                                    double *__restrict__ p_out,
+                                                    double *__restrict__ div_out,
+                                                    double *__restrict__ red) {
+    __shared__ double sh[8];
+    const int i = blockIdx.x * BX + threadIdx.x + 1;
+    const int j = blockIdx.y * BY + threadIdx.y + 1;
+    const int k = blockIdx.z + 1;
+    double dmax = 0.0;
+    if (i <= g.n[0] && j <= g.n[1] && k <= g.n[2]) {
+        const long p = pos(g, i, j, k);
+        const long c = cidx(g, i, j, k);
+        const int idx[3] = {i, j, k};
+        const double ph = phi[c];
+        const long cs[3] = {1, g.n[0], long(g.n[0]) * g.n[1]};
+        double dv = 0.0;
+#pragma unroll
+        for (int A = 0; A < 3; ++A) {
+            const int ia = idx[A];
+            const double *vi = vin + A * g.F;
+            double vp = vi[p];
+            if (ia <= g.n[A] - 1) vp -= (phi[c + cs[A]] - ph) * g.ax[A].id[ia];
+            double vm = vi[p - g.s[A]];
+            if (ia >= 2) vm -= (ph - phi[c - cs[A]]) * g.ax[A].id[ia - 1];
+            vout[A * g.F + p] = vp;
+            dv += (vp - vm) * g.ax[A].ih[ia];
+        }
+        if (p_out) p_out[c] += ph;
+        if (div_out) div_out[c] = dv;
+        dmax = fabs(dv);
+    }
+    const double r = block_max(dmax, sh);
+    if (threadIdx.x == 0 && threadIdx.y == 0)
+        red[(long(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = r;
+}
+
+// Copy the entries of v that are not interior rows' faces written by
+// k_correct (wall-normal faces, tangential wall nodes, edges, padding) from
+// v_in to v_out, zeroed (homogeneous no-slip, SIMPLE step 3).
+__global__ void k_vel_walls_zero(Geo g, double *__restrict__ vout) {
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.np[0] || j >= g.np[1] || k >= g.np[2]) return;
+    const long p = pos(g, i, j, k);
+#pragma unroll
+    for (int A = 0; A < 3; ++A) {
+        if (!cell_row(g, i, j, k) || (i == g.n[0] && A == 0) || (j == g.n[1] && A == 1) ||
+            (k == g.n[2] && A == 2))
+            vout[A * g.F + p] = 0.0;
+    }
+}
+
+// zero-walls copy: dst = src on interior faces, 0 elsewhere (velocity fields)
+__global__ void k_zero_vel_walls(Geo g, const double *__restrict__ src, double *__restrict__ dst) {
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.np[0] || j >= g.np[1] || k >= g.np[2]) return;
+    const long p = pos(g, i, j, k);
+#pragma unroll
+    for (int A = 0; A < 3; ++A)
+        dst[A * g.F + p] = face_row(g, A, i, j, k) ? src[A * g.F + p] : 0.0;
+}
+
+// Boundary-local temperature projection (eq. (21) for raw values whose
+// insulated-wall nodes equal their neighbours): keep cells, Dirichlet wall
+// nodes and edges <- 0, insulated y-wall nodes <- adjacent interior value.
+__global__ void k_ext_T(Geo g, int span_aa, const double *__restrict__ src,
+                        double *__restrict__ dst) {
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.np[0] || j >= g.np[1] || k >= g.np[2]) return;
+    const long p = pos(g, i, j, k);
+    double r = 0.0;
+    if (cell_row(g, i, j, k)) {
+        r = src[p];
+    } else if (span_aa && i >= 1 && i <= g.n[0] && k >= 1 && k <= g.n[2]) {
+        if (j == 0) r = src[p + g.s[1]];
+        if (j == g.n[1] + 1) r = src[p - g.s[1]];
+    }
+    dst[p] = r;
+}
+
+// Face control-volume weights W = d_A h_B h_C of the interior A-faces.  The
+// SIMPLE projection P is W-orthogonal (W G = -D^T V with V the cell volumes),
+// so its Euclidean transpose is P^T = W P W^-1; this kernel applies W
+// (inverse = 0) or W^-1 (inverse = 1) on interior faces and zeroes every other
+// velocity entry.  In place is allowed.
+__global__ void k_face_scale(Geo g, const double *__restrict__ src, double *__restrict__ dst,
+                             int inverse) {
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.np[0] || j >= g.np[1] || k >= g.np[2]) return;
+    const long p = pos(g, i, j, k);
+    const int idx[3] = {i, j, k};
+#pragma unroll
+    for (int A = 0; A < 3; ++A) {
+        double r = 0.0;
+        if (face_row(g, A, i, j, k)) {
+            const int B = (A + 1) % 3, C = (A + 2) % 3;
+            // 1/W = (1/d_A)(1/h_B)(1/h_C)
+            const double iw = g.ax[A].id[idx[A]] * g.ax[B].ih[idx[B]] * g.ax[C].ih[idx[C]];
+            r = inverse ? src[A * g.F + p] * iw : src[A * g.F + p] / iw;
+        }
+        dst[A * g.F + p] = r;
+    }
+}
+
+// T part of P^T: transpose of the boundary-local extension.
+__global__ void k_ext_T_T(Geo g, int span_aa, const double *__restrict__ src,
+                          double *__restrict__ dst) {
+    const int i = blockIdx.x * BX + threadIdx.x;
+    const int j = blockIdx.y * BY + threadIdx.y;
+    const int k = blockIdx.z;
+    if (i >= g.np[0] || j >= g.np[1] || k >= g.np[2]) return;
+    const long p = pos(g, i, j, k);
+    double r = 0.0;
+    if (cell_row(g, i, j, k)) {
+        r = src[p];
+        if (span_aa && j == 1) r += src[p - g.s[1]];
+        if (span_aa && j == g.n[1]) r += src[p + g.s[1]];
+    }
+    dst[p] = r;
+}
+
+dim3 box_grid(const Geo &g) {
+    return dim3((g.np[0] + BX - 1) / BX, (g.np[1] + BY - 1) / BY, g.np[2]);
+}
+dim3 cell_grid(const Geo &g) {
+    return dim3((g.n[0] + BX - 1) / BX, (g.n[1] + BY - 1) / BY, g.n[2]);
+}
+
+}  // namespace
+
+int correct_blocks(const Geo &g) {
+    dim3 gr = cell_grid(g);
+    return int(gr.x * gr.y * gr.z);
+}
+
+void launch_jacvec(const Geo &g, Coefs c, int span_aa, int ext, const double *base,
+                   const double *x, double *yv, double *yT, hipStream_t st) {
+    k_jac<0><<<box_grid(g), dim3(BX, BY), 0, st>>>(g, c, span_aa && ext, base, x, yv, yT);
+}
+
+void launch_residual(const Geo &g, Coefs c, int span_aa, const double *base, double *F,
+                     hipStream_t st) {
+    (void)span_aa;
+    k_jac<1><<<box_grid(g), dim3(BX, BY), 0, st>>>(g, c, 0, base, base, F, F + 3 * g.F);
+}
+
+void launch_jacvec_T(const Geo &g, Coefs c, int span_aa, int fold_ext, const double *base,
+                     const double *yvel, const double *yT, double *x, hipStream_t st) {
+    k_jacT<<<box_grid(g), dim3(BX, BY), 0, st>>>(g, c, fold_ext && span_aa, base, yvel, yT, x);
+}
+
+void launch_div(const Geo &g, const double *v, double *div, hipStream_t st) {
+    k_div<<<cell_grid(g), dim3(BX, BY), 0, st>>>(g, v, div);
+}
+
+void launch_correct_oop(const Geo &g, const double *vin, double *vout, const double *phi,
+                        double *p_out, double *div_out, double *red, hipStream_t st) {
+    k_vel_walls_zero<<<box_grid(g), dim3(BX, BY), 0, st>>>(g, vout);
+    k_correct<<<cell_grid(g), dim3(BX, BY), 0, st>>>(g, vin, phi, vout, p_out, div_out, red);
+}
+
+void launch_face_scale(const Geo &g, const double *src, double *dst, int inverse,
+                       hipStream_t st) {
+    k_face_scale<<<box_grid(g), dim3(BX, BY), 0, st>>>(g, src, dst, inverse);
+}
+
+void launch_ext_T(const Geo &g, int span_aa, const double *src, double *dst, hipStream_t st) {
+    k_ext_T<<<box_grid(g), dim3(BX, BY), 0, st>>>(g, span_aa, src, dst);
+}
+
+void launch_ext_T_T(const Geo &g, int span_aa, const double *src, double *dst, hipStream_t st) {
+    k_ext_T_T<<<box_grid(g), dim3(BX, BY), 0, st>>>(g, span_aa, src, dst);
+}
+
+void launch_zero_vel_walls(const Geo &g, const double *src, double *dst, hipStream_t st) {
+    k_zero_vel_walls<<<box_grid(g), dim3(BX, BY), 0, st>>>(g, src, dst);
+}
+
+}  // namespace fvk

@@ -1,0 +1,137 @@
+"""Parity of the HIP path (through the C ABI) with the CPU FP64 oracle on the
+same seeded inputs.  Bar: relative max-norm error <= 1e-10 in FP64."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ops
+from oracle.grid import TANH, UNIFORM, SINE
+from tests.gpu_util import base, dev, krylov_input, rel_err, setup
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::UserWarning")]
+
+TOL = 1e-10
+CASES = [((6, 5, 7), TANH, 1.5), ((20, 20, 20), UNIFORM, 0.0), ((17, 33, 9), SINE, 0.12),
+         ((40, 40, 40), TANH, 1.5)]
+IDS = ["6x5x7-tanh", "20-uniform", "17x33x9-sine", "40-tanh"]
+
+
+@pytest.mark.parametrize("n,kind,s", CASES, ids=IDS)
+@pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
+def test_residual_and_jacvec(fvk, n, kind, s, bc):
+    print(f"case residual/jacvec n={n} kind={kind} bc={bc}", flush=True)
+    g, orc, ctx = setup(n, kind, s, bc)
+    U = base(g, bc)
+    x = krylov_input(g, orc, 2000, project=False)
+    F = ctx.fv_residual(dev(U))
+    assert rel_err(F, ops.residual(g, orc.prm, U)) < TOL
+    PF = ctx.fv_residual(dev(U), project=True)
+    assert rel_err(PF, orc.residual(U, project=True)) < TOL
+    Jx = ctx.fv_jacvec(dev(U), dev(x))
+    assert rel_err(Jx, ops.jacvec(g, orc.prm, U, x)) < TOL
+    JTx = ctx.fv_jacvec(dev(U), dev(x), transpose=True)
+    assert rel_err(JTx, orc.jacvec_T(U, x)) < TOL
+
+
+@pytest.mark.parametrize("n,kind,s", CASES, ids=IDS)
+@pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
+def test_projection(fvk, n, kind, s, bc):
+    print(f"case projection n={n} kind={kind} bc={bc}", flush=True)
+    g, orc, ctx = setup(n, kind, s, bc)
+    x = krylov_input(g, orc, 2001, project=False)
+    Px = ctx.project(dev(x))
+    assert rel_err(Px, orc.project(x)) < TOL
+    PTx = ctx.project(dev(x), transpose=True)
+    assert rel_err(PTx, orc.project_T(x)) < TOL
+
+
+@pytest.mark.parametrize("n,kind,s", CASES, ids=IDS)
+@pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
+def test_simple_krylov_vec(fvk, n, kind, s, bc):
+    print(f"case krylov_vec n={n} kind={kind} bc={bc}", flush=True)
+    g, orc, ctx = setup(n, kind, s, bc)
+    U = base(g, bc)
+    for seed in (2000, 2001):
+        x = krylov_input(g, orc, seed)
+        y, passes, dmax = ctx.simple_krylov_vec(dev(U), dev(x), info=True)
+        ref, _, rpasses, rdmax = orc.krylov_vec(U, x, with_info=True)
+        assert passes == 1 and rpasses == 1
+        assert dmax < 1e-9
+        assert rel_err(y, ref) < TOL
+        yT = ctx.simple_krylov_vec(dev(U), dev(x), transpose=True)
+        assert rel_err(yT, orc.krylov_vec_T(U, x)) < TOL
+    # pressure output: accumulated phi, zero volume-weighted mean
+    p = torch.zeros(g.n[::-1], dtype=torch.float64, device="cuda")
+    ctx.simple_krylov_vec(dev(U), dev(x), p_out=p)
+    _, pref, _, _ = orc.krylov_vec(U, x, with_info=True)
+    assert rel_err(p, pref) < TOL
+
+
+def test_asynchronous_calls_record_divergence(fvk):
+    g, orc, ctx = setup((12, 12, 12), TANH, 1.5, 0)
+    U = dev(base(g, 0))
+    x = dev(krylov_input(g, orc, 2002))
+    ctx.simple_stats()
+    y = ctx.empty()
+    for _ in range(5):
+        ctx.simple_krylov_vec(U, x, out=y)
+    dmax, nbad = ctx.simple_stats()
+    assert nbad == 0 and 0 <= dmax < 1e-9
+    assert rel_err(y, orc.krylov_vec(base(g, 0), krylov_input(g, orc, 2002))) < TOL
+
+
+@pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
+def test_mixed_precision_krylov_vec(fvk, bc):
+    g, orc, ctx = setup((24, 20, 28), TANH, 1.5, bc, prec=1)
+    U = base(g, bc)
+    x = krylov_input(g, orc, 2003)
+    y, passes, dmax = ctx.simple_krylov_vec(dev(U), dev(x), info=True)
+    ref = orc.krylov_vec(U, x)
+    assert 2 <= passes <= 3 and dmax < 1e-9
+    assert rel_err(y, ref) < 1e-10
+    yT = ctx.simple_krylov_vec(dev(U), dev(x), transpose=True)
+    assert rel_err(yT, orc.krylov_vec_T(U, x)) < 1e-9
+
+
+def test_vector_kernels(fvk):
+    g, orc, ctx = setup((9, 8, 7), TANH, 1.5, 0)
+    rng = np.random.default_rng(0)
+    m = 13
+    Vh = rng.standard_normal((m + 1, ctx.N))
+    V = torch.as_tensor(Vh).cuda()
+    w = V[m].clone()
+    d = ctx.multidot(V, m, w)
+    assert np.max(np.abs(d - Vh[:m] @ Vh[m])) < 1e-12 * np.abs(Vh[:m] @ Vh[m]).max() * 10
+    c = rng.standard_normal(m)
+    ctx.multiaxpy(w, 0.5, V, c)
+    assert rel_err(w, torch.as_tensor(0.5 * Vh[m] + c @ Vh[:m])) < 1e-13
+    Q = rng.standard_normal((m, 5))
+    ctx.basis_rotate(V, Q)
+    assert rel_err(V[:5], torch.as_tensor(Q.T @ Vh[:m])) < 1e-13
+    assert rel_err(V[5:], torch.as_tensor(Vh[5:])) == 0.0
+
+
+@pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
+def test_arnoldi_step(fvk, bc):
+    g, orc, ctx = setup((10, 9, 11), TANH, 1.5, bc)
+    U = base(g, bc)
+    x0 = krylov_input(g, orc, 5000)
+    V = torch.zeros(4, ctx.N, dtype=torch.float64, device="cuda")
+    V[0] = dev(x0).reshape(-1)
+    Vo = [x0.reshape(-1).numpy()]
+    for j in range(3):
+        h, brk = ctx.arnoldi_step(dev(U), V, j)
+        assert not brk
+        w = orc.krylov_vec(U, torch.as_tensor(Vo[j].reshape(orc.shape4))).reshape(-1).numpy()
+        hr = np.array([Vo[q] @ w for q in range(j + 1)])
+        w = w - sum(hr[q] * Vo[q] for q in range(j + 1))
+        h2 = np.array([Vo[q] @ w for q in range(j + 1)])
+        w = w - sum(h2[q] * Vo[q] for q in range(j + 1))
+        hr = hr + h2
+        nr = np.linalg.norm(w)
+        Vo.append(w / nr)
+        assert np.max(np.abs(h[:j + 1] - hr)) < 1e-10 * np.abs(hr).max()
+        assert abs(h[j + 1] - nr) < 1e-10 * nr
+        assert rel_err(V[j + 1], torch.as_tensor(Vo[j + 1])) < 1e-9
+    G = (V @ V.T).cpu().numpy()
+    assert np.max(np.abs(G - np.eye(4))) < 1e-13
