@@ -18,12 +18,17 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 struct Mfma;
+// Operands (both types): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
+// Result row of accumulator register r in lane l (column l % 16) differs:
+// f64 places row 4 r + l / 16, f32 places row 4 (l / 16) + r (checked by an
+// in-bounds probe on gfx950).
 template <>
 struct Mfma<double> {
     typedef d4 acc;
     static __device__ __forceinline__ acc op(double a, double b, acc c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
 };
 template <>
 struct Mfma<float> {
@@ -31,6 +36,7 @@ struct Mfma<float> {
     static __device__ __forceinline__ acc op(float a, float b, acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
 constexpr int TM = 32, TN = 64, KC = 16, NT = 256;
@@ -106,7 +112,7 @@ __global__ __launch_bounds__(NT) void k_axis(const Tc *__restrict__ M, AxisView 
         const long ca = col_addr(v, col);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const int row = row0 + wr + 4 * (lane >> 4) + r;
+            const int row = row0 + wr + Mfma<Tc>::row(lane, r);
             if (row >= na) continue;
             Tc val = acc[r];
             if (SCALE) {
