@@ -1,0 +1,256 @@
+#!/usr/bin/env python
+"""Throughput of the Krylov-vector hot path on one MI355X.
+
+Workload (one step): the 100^3 throughput configuration -- tanh-stretched grid
+(beta = 1.5), Pr = 0.71, Gr = 1e6, a seeded divergence-free synthetic base
+flow, and 64 seeded unit-norm Krylov vectors in the constraint subspace; one
+step applies simple_krylov_vec (Jacobian stencil, SIMPLE pass with the TPF
+Poisson solve, temperature projection) to all 64 vectors for both spanwise
+wall variants (conducting CC and insulated AA), i.e. 128 Krylov vectors, all
+FP64.  Inputs are resident in device memory before the timed region.
+
+Prints one JSON line: value = Krylov vectors per second, a roofline entry for
+the dominant kernel (timed live with HIP events on the library's stream) and
+a CPU baseline of the oracle on a bounded sample of the same workload.
+
+Usage: python bench.py [--steps K] [--warmup W] [--n N] [--nvec M]
+       [--no-cpu-baseline] [--extra]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("Krylov vectors/s at 100^3 & 256^3 (FP64 vs mixed+adjoint) at stated "
+          "λ error")
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_PEAK_TFS = 78.6         # MI355X dense FP64 (vector and matrix)
+FP32_PEAK_TFS = 157.3        # MI355X dense FP32 matrix
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_inputs(fvk, torch, n, nvec, bc, prec):
+    from paper_1905_11601_amd import inputs
+    ctx = fvk.Ctx(n, grid=fvk.TANH, s=1.5, span_bc=bc, Gr=1e6, Pr=0.71, prec=prec)
+    f, c, h = ctx.coords()
+    base = torch.as_tensor(inputs.synthetic_base(f, c, h, bc)).cuda()
+    X = torch.empty((nvec,) + ctx.shape4, dtype=torch.float64, device="cuda")
+    for q in range(nvec):
+        raw = torch.as_tensor(inputs.random_fields(ctx.n, 2000 + q)).cuda()
+        ctx.project(raw, out=X[q])
+        X[q] /= ctx.dot(X[q], X[q]) ** 0.5
+    return ctx, base, X
+
+
+def stencil_bytes_per_point():
+    # jacvec: reads base (4 fields) + x (4 fields), writes the momentum
+    # predictor (3 fields) + projected T (1 field), every stored point, FP64
+    return (8 + 4) * 8
+
+
+def cpu_baseline(n, nvec_sample):
+    """The oracle on the host cores: simple_krylov_vec of the same workload on
+    a bounded sample (nvec_sample vectors, CC walls)."""
+    import torch
+    from oracle import ops
+    from oracle.grid import Grid, TANH
+    from oracle.krylov import Oracle
+    from paper_1905_11601_amd import inputs
+    g = Grid(n, kind=TANH, s=1.5)
+    orc = Oracle(g, ops.Params(1e6, 0.71), 0)
+    f = tuple(a.f for a in g.ax)
+    c = tuple(a.c for a in g.ax)
+    h = tuple(a.h for a in g.ax)
+    U = torch.as_tensor(inputs.synthetic_base(f, c, h, 0))
+    xs = []
+    for q in range(nvec_sample):
+        x = orc.project(torch.as_tensor(inputs.random_fields(g.n, 2000 + q)))
+        xs.append(x / torch.linalg.norm(x))
+    orc.krylov_vec(U, xs[0])                      # warm-up
+    t0 = time.perf_counter()
+    for x in xs:
+        orc.krylov_vec(U, x)
+    dt = time.perf_counter() - t0
+    return {"value": nvec_sample / dt, "unit": "Krylov vectors/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"{nvec_sample} simple_krylov_vec calls at {n}^3, CC walls, "
+                      f"PyTorch CPU FP64 oracle ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=100)
+    ap.add_argument("--nvec", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=64)
+    ap.add_argument("--extra", action="store_true",
+                    help="also report mixed-precision, adjoint and Arnoldi-step rates")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is a design note, not an implementation", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1905_11601_amd as fvk
+
+    n, nvec = args.n, args.nvec
+    log(f"setup {n}^3, {nvec} vectors x 2 wall variants")
+    runs = [make_inputs(fvk, torch, n, nvec, bc, fvk.FP64) for bc in (fvk.CC, fvk.AA)]
+    Ys = [torch.empty_like(X) for (_, _, X) in runs]
+
+    def step():
+        for (ctx, base, X), Y in zip(runs, Ys):
+            for q in range(nvec):
+                ctx.simple_krylov_vec(base, X[q], out=Y[q])
+
+    for ctx, _, _ in runs:
+        ctx.simple_stats()
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        step()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = ev0.elapsed_time(ev1)
+    nvec_total = 2 * nvec * args.steps
+    value = nvec_total / (ms_total / 1e3)
+    max_div = 0.0
+    for ctx, _, _ in runs:
+        d, bad = ctx.simple_stats()
+        if bad:
+            raise SystemExit(f"{bad} Krylov vectors failed the divergence test")
+        max_div = max(max_div, d)
+
+    # ---- roofline of the dominant kernel: the same steps again with HIP-event
+    # stage timing on the library's stream
+    for ctx, _, _ in runs:
+        ctx.set_timing(("jacvec", "div", "transform", "correct"))
+    for _ in range(args.steps):
+        step()
+    stages = {}
+    for ctx, _, _ in runs:
+        for k, (ms, cnt) in ctx.timing_read().items():
+            a = stages.setdefault(k, [0.0, 0])
+            a[0] += ms
+            a[1] += cnt
+        ctx.set_timing(())
+    log("stage times (ms total / launches): " + json.dumps(stages))
+    ctx0 = runs[0][0]
+    npts = (n + 2) ** 3
+    ncell = n ** 3
+    per = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
+    dominant = max(("jacvec", "transform", "correct", "div"), key=lambda k: stages[k][0])
+    if dominant == "transform":
+        flops = 2.0 * n * ncell                   # one axis transform: 2 N flops per cell
+        achieved = flops / (per["transform"] * 1e-3) / 1e12
+        roof = {"kernel": "k_axis (TPF axis transform, FP64 MFMA)", "bound": "mfma",
+                "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                "frac": achieved / FP64_PEAK_TFS, "traffic": None,
+                "per_launch_us": per["transform"] * 1e3}
+    else:
+        bytes_per = {"jacvec": stencil_bytes_per_point() * npts,
+                     "correct": (3 + 3 + 1) * 8 * ncell + 3 * 8 * npts,
+                     "div": (3 * 8 + 8) * ncell}[dominant]
+        achieved = bytes_per / (per[dominant] * 1e-3) / 1e9
+        roof = {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "per_launch_us": per[dominant] * 1e3}
+    roof["stages_us_per_launch"] = {k: v * 1e3 for k, v in per.items() if stages[k][1]}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Krylov vectors/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_total / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"simple_krylov_vec, {n}^3 tanh-stretched (beta 1.5) staggered FV "
+                               f"cube, Pr 0.71, Gr 1e6, synthetic divergence-free base flow, "
+                               f"{nvec} seeded unit Krylov vectors x (CC, AA) spanwise walls, FP64",
+                   "grid": n, "vectors_per_step": 2 * nvec, "parallelism": "single GPU",
+                   "max_div_after_simple": max_div},
+        "roofline": roof,
+        "wall_s": wall,
+    }
+    if args.extra:
+        out["extra"] = extra_rates(fvk, torch, runs, args)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_sample)
+    print(json.dumps(out))
+
+
+def timed(torch, fn, reps):
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(reps):
+        fn()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / reps
+
+
+def extra_rates(fvk, torch, runs, args):
+    """Mixed-precision and transposed (adjoint) Krylov-vector rates on the same
+    vectors, and the Arnoldi-step rate at Krylov dimension 40."""
+    ctx, base, X = runs[0]
+    nvec = X.shape[0]
+    Y = torch.empty_like(X)
+    res = {}
+
+    def run(transpose):
+        for q in range(nvec):
+            ctx.simple_krylov_vec(base, X[q], out=Y[q], transpose=transpose)
+
+    run(False)
+    res["fp64_vec_per_s"] = nvec / (timed(torch, lambda: run(False), 2) / 1e3)
+    ref = Y.clone()
+    ctx.set_precision(fvk.MIXED)
+    run(False)
+    res["mixed_vec_per_s"] = nvec / (timed(torch, lambda: run(False), 2) / 1e3)
+    res["mixed_max_rel_diff_vs_fp64"] = float(((Y - ref).abs().max() / ref.abs().max()).item())
+    run(True)
+    res["mixed_adjoint_vec_per_s"] = nvec / (timed(torch, lambda: run(True), 2) / 1e3)
+    ctx.set_precision(fvk.FP64)
+    run(True)
+    res["fp64_adjoint_vec_per_s"] = nvec / (timed(torch, lambda: run(True), 2) / 1e3)
+    m = 40
+    V = torch.zeros((m + 1, ctx.N), dtype=torch.float64, device="cuda")
+    V[0] = X[0].reshape(-1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(m):
+        ctx.arnoldi_step(base, V, j)
+    torch.cuda.synchronize()
+    res["arnoldi_steps_per_s_m40"] = m / (time.perf_counter() - t0)
+    return res
+
+
+if __name__ == "__main__":
+    main()

@@ -141,6 +141,23 @@ fvk_status fvk_simple_stats(fvk_ctx *ctx, double *max_div, int *n_unconverged);
 fvk_status arnoldi_step(fvk_ctx *ctx, const double *base, double *V, size_t ldv, int j,
                         double *h_col, int transpose);
 
+/* ---------------------------------------------------------------- tracing */
+
+/* Stages of the Krylov-vector path timed with HIP events on the context's
+ * stream when tracing is on: the Jacobian stencil (forward or transposed,
+ * including the fused temperature projection), the divergence of the momentum
+ * predictor, one axis transform of the TPF Poisson solve (six per solve), the
+ * velocity correction with its fused divergence check, and the Gram-Schmidt
+ * kernels of arnoldi_step. */
+enum { FVK_STAGE_JACVEC = 0, FVK_STAGE_DIV = 1, FVK_STAGE_TRANSFORM = 2, FVK_STAGE_CORRECT = 3,
+       FVK_STAGE_ORTHO = 4, FVK_NSTAGES = 5 };
+/* mask: bit s enables stage s (0 = off).  Each enabled launch records two
+ * events (a few microseconds of queue overhead each). */
+fvk_status fvk_set_timing(fvk_ctx *ctx, int mask);
+/* Synchronises, returns accumulated milliseconds and launch counts per stage
+ * (host arrays of FVK_NSTAGES entries) since the last read, and resets. */
+fvk_status fvk_timing_read(fvk_ctx *ctx, double *ms, int *counts);
+
 /* ------------------------------------------------------- vector kernels */
 
 /* out[q] = <V_q, w> for q < m over n doubles (host out). */

@@ -164,6 +164,20 @@ class Ctx:
         self._check(self.lib.fvk_simple_stats(self.h, ctypes.byref(d), ctypes.byref(k)))
         return d.value, k.value
 
+    STAGES = ("jacvec", "div", "transform", "correct", "ortho")
+
+    def set_timing(self, stages=()):
+        mask = 0
+        for s_ in stages:
+            mask |= 1 << self.STAGES.index(s_)
+        self._check(self.lib.fvk_set_timing(self.h, mask))
+
+    def timing_read(self):
+        ms = (ctypes.c_double * 5)()
+        cnt = (ctypes.c_int * 5)()
+        self._check(self.lib.fvk_timing_read(self.h, ms, cnt))
+        return {s_: (ms[q], cnt[q]) for q, s_ in enumerate(self.STAGES)}
+
     def arnoldi_step(self, base, V, j, transpose=False):
         """V: (m+1, N) float64 CUDA tensor (rows are basis vectors)."""
         if V.dim() != 2 or V.shape[1] != self.N or not V.is_contiguous() or j + 1 >= V.shape[0]:

@@ -51,6 +51,8 @@ SIGNATURES = {
                                   P(c_int), P(c_double)]),
     "fvk_simple_stats": (c_int, [c_void_p, P(c_double), P(c_int)]),
     "arnoldi_step": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_int, P(c_double), c_int]),
+    "fvk_set_timing": (c_int, [c_void_p, c_int]),
+    "fvk_timing_read": (c_int, [c_void_p, P(c_double), P(c_int)]),
     "fvk_multidot": (c_int, [c_void_p, c_void_p, c_size_t, c_int, c_void_p, c_size_t,
                              P(c_double)]),
     "fvk_multiaxpy": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_size_t, c_int,

@@ -112,13 +112,17 @@ fvk_status simple_forward(fvk_ctx *ctx, double *vin, double *vout, double *p_out
     const int fixed = fp32 ? ctx->mixed_passes : 1;
     const int nred = correct_blocks(g);
     if (p_out) launch_fill(p_out, 0.0, ctx->ncell, st);
+    timing_begin(ctx, FVK_STAGE_DIV);
     launch_div(g, vin, w.div, st);
+    timing_end(ctx, FVK_STAGE_DIV);
     double *src = vin, *dst = vout;
     int k = 0;
     double dmax = 0.0;
     while (true) {
         tpf_solve(ctx, w.div, w.phi, fp32, st);
+        timing_begin(ctx, FVK_STAGE_CORRECT);
         launch_correct_oop(g, src, dst, w.phi, p_out, w.div, w.red, st);
+        timing_end(ctx, FVK_STAGE_CORRECT);
         ++k;
         const bool last_fixed = !sync && k >= fixed;
         launch_max_reduce(w.red, nred, w.dev_scalars, last_fixed ? w.dev_scalars + 1 : nullptr,
@@ -161,7 +165,69 @@ fvk_status simple_transpose(fvk_ctx *ctx, const double *y, double *z, bool sync,
 
 }  // namespace
 
+namespace fvk {
+
+static constexpr size_t kTimingPairs = 8192;
+
+static void timing_harvest(fvk_ctx *ctx) {
+    Timing &t = ctx->tm;
+    if (t.used == 0) return;
+    (void)hipEventSynchronize(t.ev[2 * (t.used - 1) + 1]);
+    for (size_t q = 0; q < t.used; ++q) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, t.ev[2 * q], t.ev[2 * q + 1]) == hipSuccess) {
+            t.ms[t.stage[q]] += ms;
+            t.count[t.stage[q]] += 1;
+        }
+    }
+    t.used = 0;
+}
+
+void timing_begin(fvk_ctx *ctx, int stage) {
+    Timing &t = ctx->tm;
+    if (!(t.mask & (1 << stage))) return;
+    if (t.used == kTimingPairs) timing_harvest(ctx);
+    (void)hipEventRecord(t.ev[2 * t.used], ctx->stream);
+    t.stage[t.used] = stage;
+}
+
+void timing_end(fvk_ctx *ctx, int stage) {
+    Timing &t = ctx->tm;
+    if (!(t.mask & (1 << stage))) return;
+    (void)hipEventRecord(t.ev[2 * t.used + 1], ctx->stream);
+    ++t.used;
+}
+
+}  // namespace fvk
+
 extern "C" {
+
+fvk_status fvk_set_timing(fvk_ctx *ctx, int mask) {
+    if (!ctx || mask < 0 || mask >= (1 << FVK_NSTAGES)) return FVK_EINVAL;
+    Timing &t = ctx->tm;
+    if (mask && t.ev.empty()) {
+        t.ev.resize(2 * kTimingPairs);
+        t.stage.resize(kTimingPairs);
+        for (auto &e : t.ev) HIPCHK(ctx, hipEventCreate(&e));
+    }
+    timing_harvest(ctx);
+    t.mask = mask;
+    return FVK_OK;
+}
+
+fvk_status fvk_timing_read(fvk_ctx *ctx, double *ms, int *counts) {
+    if (!ctx) return FVK_EINVAL;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    timing_harvest(ctx);
+    Timing &t = ctx->tm;
+    for (int s = 0; s < FVK_NSTAGES; ++s) {
+        if (ms) ms[s] = t.ms[s];
+        if (counts) counts[s] = t.count[s];
+        t.ms[s] = 0.0;
+        t.count[s] = 0;
+    }
+    return FVK_OK;
+}
 
 fvk_status fvk_create(fvk_ctx **out, int nx, int ny, int nz, int grid_kind, double s, int span_bc,
                       double Gr, double Pr, int prec, void *hip_stream) {
@@ -424,7 +490,9 @@ fvk_status simple_krylov_vec(fvk_ctx *ctx, const double *base, const double *x, 
     const int aa = ctx->bc == FVK_SPAN_AA;
     if (!transpose) {
         // momentum predictor + temperature RHS (eqs (11)-(12)), T part final
+        timing_begin(ctx, FVK_STAGE_JACVEC);
         launch_jacvec(g, ctx->co, aa, 1, base, x, w.vtmp, y + 3 * F, st);
+        timing_end(ctx, FVK_STAGE_JACVEC);
         CHECK_LAUNCH(ctx);
         const bool sync = passes || max_div;
         int k = 0;
@@ -441,7 +509,9 @@ fvk_status simple_krylov_vec(fvk_ctx *ctx, const double *base, const double *x, 
     if (passes) *passes = k;
     if (max_div) *max_div = dmax;
     if (s != FVK_OK) return s;
+    timing_begin(ctx, FVK_STAGE_JACVEC);
     launch_jacvec_T(g, ctx->co, aa, 1, base, w.vtmp, x + 3 * F, y, st);
+    timing_end(ctx, FVK_STAGE_JACVEC);
     CHECK_LAUNCH(ctx);
     return FVK_OK;
 }
@@ -510,6 +580,7 @@ fvk_status arnoldi_step(fvk_ctx *ctx, const double *base, double *V, size_t ldv,
     double *hr = ctx->ws.dev_scalars + 8 + 1001;  // re-orthogonalisation coefficients
     double *nrm = ctx->ws.dev_scalars + 4;
     // classical Gram-Schmidt, then one full re-orthogonalisation pass (CGS2)
+    timing_begin(ctx, FVK_STAGE_ORTHO);
     launch_multidot(V, ldv, m, wv, n, ctx->ws.red, nb, st);
     launch_reduce_partials(ctx->ws.red, nb, m, h, 0, st);
     launch_multiaxpy(wv, 1.0, -1.0, V, ldv, m, h, n, st);
@@ -520,6 +591,7 @@ fvk_status arnoldi_step(fvk_ctx *ctx, const double *base, double *V, size_t ldv,
     launch_multidot(wv, ldv, 1, wv, n, ctx->ws.red, nb, st);
     launch_reduce_partials(ctx->ws.red, nb, 1, nrm, 0, st);
     launch_scale_inv_sqrt(wv, nrm, n, st);
+    timing_end(ctx, FVK_STAGE_ORTHO);
     CHECK_LAUNCH(ctx);
     double nrm2 = 0.0;
     s = read_back(ctx, h, h_col, m);

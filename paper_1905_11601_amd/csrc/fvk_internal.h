@@ -48,6 +48,16 @@ struct Eig1D {
     std::vector<double> lam, E, Einv;
 };
 
+// HIP-event stage timing (see fvk_set_timing).
+struct Timing {
+    int mask = 0;
+    std::vector<hipEvent_t> ev;          // pool, pairs (start, stop)
+    std::vector<int> stage;              // stage of each recorded pair
+    size_t used = 0;                     // pairs recorded since the last harvest
+    double ms[8] = {0};
+    int count[8] = {0};
+};
+
 struct Workspace {
     double *geo = nullptr;          // packed AxisDev arrays
     double *div = nullptr;          // n cells (compact), also r/V in transposed passes
@@ -85,11 +95,16 @@ struct fvk_ctx {
     fvk::Eig1D eig[3];
     fvk::Geo geo{};
     fvk::Workspace ws;
+    fvk::Timing tm;
     size_t ncell = 0;
     std::string err;
 };
 
 namespace fvk {
+
+// ---- tracing (capi.cpp): bracket one launch of `stage` with events
+void timing_begin(fvk_ctx *ctx, int stage);
+void timing_end(fvk_ctx *ctx, int stage);
 
 // ---- host utilities (eig.cpp)
 void build_axis(AxisHost &a, int n, int kind, double s);
