@@ -45,7 +45,7 @@ def make_inputs(fvk, torch, n, nvec, bc, prec):
     for q in range(nvec):
         raw = torch.as_tensor(inputs.random_fields(ctx.n, 2000 + q)).cuda()
         ctx.project(raw, out=X[q])
-        X[q] /= ctx.dot(X[q], X[q]) ** 0.5
+        ctx.normalize(X[q])
     return ctx, base, X
 
 

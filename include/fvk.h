@@ -166,6 +166,8 @@ fvk_status fvk_multidot(fvk_ctx *ctx, const double *V, size_t ldv, int m, const 
 /* w <- alpha w + sum_q c[q] V_q (c host, m entries). */
 fvk_status fvk_multiaxpy(fvk_ctx *ctx, double *w, double alpha, const double *V, size_t ldv,
                          int m, const double *c, size_t n);
+/* y <- a x + b y over n doubles (x == y allowed: scaling). */
+fvk_status fvk_axpby(fvk_ctx *ctx, double *y, double a, const double *x, double b, size_t n);
 /* V[:, 0..k) <- V[:, 0..m) Q with Q host, column-major m x k (k <= m), in place
  * (Krylov-Schur restart / Ritz vector assembly). */
 fvk_status fvk_basis_rotate(fvk_ctx *ctx, double *V, size_t ldv, int m, const double *Q, int k,

@@ -205,6 +205,18 @@ class Ctx:
                                            len(c), c.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                            self.N))
 
+    def axpby(self, y, a, x, b):
+        """y <- a x + b y (library kernel); x may be y (scaling)."""
+        if y.numel() != x.numel() or not (y.is_contiguous() and x.is_contiguous()):
+            raise ValueError("axpby: contiguous tensors of equal size")
+        self._check(self.lib.fvk_axpby(self.h, _ptr(y), float(a), _ptr(x), float(b), y.numel()))
+        return y
+
+    def normalize(self, x):
+        nrm = self.dot(x, x) ** 0.5
+        self.axpby(x, 1.0 / nrm, x, 0.0)
+        return nrm
+
     def basis_rotate(self, V, Q):
         """V[:k] <- (V[:m]^T Q)^T with Q (m, k) real."""
         Q = np.asfortranarray(Q, dtype=np.float64)

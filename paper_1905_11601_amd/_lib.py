@@ -57,6 +57,7 @@ SIGNATURES = {
                              P(c_double)]),
     "fvk_multiaxpy": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_size_t, c_int,
                               P(c_double), c_size_t]),
+    "fvk_axpby": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_double, c_size_t]),
     "fvk_basis_rotate": (c_int, [c_void_p, c_void_p, c_size_t, c_int, P(c_double), c_int,
                                  c_size_t]),
     "fvk_newton_defaults": (None, [P(NewtonOpts)]),

@@ -552,9 +552,16 @@ fvk_status fvk_multiaxpy(fvk_ctx *ctx, double *w, double alpha, const double *V,
     return FVK_OK;
 }
 
+fvk_status fvk_axpby(fvk_ctx *ctx, double *y, double a, const double *x, double b, size_t n) {
+    if (!ctx || !y || !x || n == 0) return FVK_EINVAL;
+    launch_axpby(y, a, x, b, n, ctx->stream);
+    CHECK_LAUNCH(ctx);
+    return FVK_OK;
+}
+
 fvk_status fvk_basis_rotate(fvk_ctx *ctx, double *V, size_t ldv, int m, const double *Q, int k,
                             size_t n) {
-    if (!ctx || !V || !Q || m < 1 || k < 1 || k > m || m > 400 || n == 0) return FVK_EINVAL;
+    if (!ctx || !V || !Q || m < 1 || k < 1 || k > m || m > 200 || n == 0) return FVK_EINVAL;
     fvk_status s = write_coefs(ctx, Q, size_t(m) * k);
     if (s != FVK_OK) return s;
     launch_basis_rotate(V, ldv, m, ctx->ws.coef_dev, k, n, ctx->stream);

@@ -1,0 +1,118 @@
+"""Rightmost eigenvalues of the Krylov operator A (or A^T) by Krylov-Schur
+restarted Arnoldi (Stewart, SIAM J. Matrix Anal. Appl. 23, 2001).
+
+The paper computes the leading eigenpairs of eq. (10) with ARPACK / HSL EB13
+in the "single run" mode that the SIMPLE-based Krylov vectors allow (Sec. 3.1);
+this driver plays that role.  Each Arnoldi step is the library's arnoldi_step
+(Krylov vector + CGS2 orthogonalisation in HIP kernels); restarts rotate the
+device-resident basis with fvk_basis_rotate.  Only the small (m x m)
+Rayleigh quotient is handled on the host (real Schur form, scipy).
+
+Convergence: a Ritz pair (theta, V x) is accepted when the residual
+|| A V x - theta V x || / || V x || = |b^T x| is below ``tol`` (the paper
+monitors || J X - lambda X || / || X || < 1e-10 after convergence).
+"""
+import numpy as np
+import scipy.linalg as sla
+
+
+def _order(lam):
+    lam = np.asarray(lam)
+    scale = max(float(np.max(np.abs(lam))), 1e-300) if lam.size else 1.0
+    re = np.round(lam.real / (1e-9 * scale))
+    return np.lexsort((-lam.imag, -re))
+
+
+class EigResult:
+    def __init__(self, lam, X, res, restarts, nvec, converged):
+        self.lam, self.X, self.res = lam, X, res
+        self.restarts, self.nvec, self.converged = restarts, nvec, converged
+
+
+def krylov_schur(ctx, base, k, m, v0, tol=1e-10, max_restarts=200, transpose=False,
+                 vectors=True, log=None):
+    """k rightmost eigenvalues (largest real part) of A (transpose: A^T).
+
+    v0: (N,) or ctx.shape4 float64 CUDA tensor (start vector; for A it should
+    lie in the constraint subspace, e.g. the output of ctx.project).
+    Returns EigResult with lam sorted by (-Re, -Im); X (if vectors) is a
+    (kk, N) complex128 CUDA tensor of unit Ritz vectors."""
+    import torch
+    if not (0 < k < m):
+        raise ValueError("need 0 < k < m")
+    N = ctx.N
+    V = torch.zeros((m + 1, N), dtype=torch.float64, device=ctx.device)
+    V[0] = v0.reshape(-1)
+    ctx.normalize(V[0])
+    H = np.zeros((m + 1, m))
+    p = 0
+    nvec = 0
+    lam = res = None
+    kept = min(m - 1, max(k + 2, (m + k) // 2))
+    for restart in range(max_restarts + 1):
+        for j in range(p, m):
+            h, brk = ctx.arnoldi_step(base, V, j, transpose=transpose)
+            nvec += 1
+            H[:j + 2, j] = h
+            if brk:
+                raise RuntimeError("Arnoldi breakdown (invariant subspace)")
+        Hm = H[:m, :m]
+        b = H[m, :m].copy()
+        evals = np.linalg.eigvals(Hm)
+        order = _order(evals)
+        evals = evals[order]
+        # residuals of the k wanted Ritz pairs: |b^T x| for unit eigenvectors x
+        w, Xh = np.linalg.eig(Hm)
+        o2 = _order(w)
+        w, Xh = w[o2], Xh[:, o2]
+        Xh = Xh / np.linalg.norm(Xh, axis=0, keepdims=True)
+        res = np.abs(b @ Xh)
+        lam = w
+        nconv = int(np.sum(res[:k] < tol))
+        if log:
+            log(f"restart {restart}: nvec {nvec}, lead {w[0]:.10g}, res {res[:k].max():.2e}")
+        if nconv >= k or restart == max_restarts:
+            break
+        # Krylov-Schur truncation: keep the `kept` rightmost Ritz values
+        thr = evals[kept - 1].real
+        scale = 1e-12 * max(1.0, np.abs(evals).max())
+        S, Q, sdim = sla.schur(Hm, output='real', sort=lambda re, im: re >= thr - scale)
+        p = int(sdim)
+        if p >= m or p == 0:
+            p = kept
+        ctx.basis_rotate(V, Q[:, :p])
+        V[p] = V[m]
+        H[:] = 0.0
+        H[:p, :p] = S[:p, :p]
+        H[p, :p] = b @ Q[:, :p]
+    converged = bool(np.all(res[:k] < tol))
+    kk = k
+    # keep both members of a conjugate pair cut at position k
+    if kk < len(lam) and lam[kk - 1].imag != 0 and abs(lam[kk] - np.conj(lam[kk - 1])) <= \
+            1e-8 * abs(lam[kk - 1]):
+        kk += 1
+    X = None
+    if vectors:
+        if 2 * kk > m:
+            raise ValueError("need 2 * (number of Ritz vectors) <= m")
+        # real and imaginary parts in one in-place rotation of the basis
+        M = np.concatenate([Xh[:, :kk].real, Xh[:, :kk].imag], axis=1)
+        ctx.basis_rotate(V, M)
+        X = torch.complex(V[:kk].clone(), V[kk:2 * kk].clone())
+    return EigResult(lam[:kk], X, res[:kk], restart, nvec, converged)
+
+
+def ritz_residual(ctx, base, lam, x, transpose=False):
+    """|| A x - lam x || / || x || for a complex CUDA vector x (two real
+    Krylov-vector applications)."""
+    import torch
+    XX = torch.stack([x.real.reshape(-1), x.imag.reshape(-1)]).contiguous()
+    xr, xi = XX[0].reshape(ctx.shape4), XX[1].reshape(ctx.shape4)
+    lr, li = float(np.real(lam)), float(np.imag(lam))
+    rr = ctx.simple_krylov_vec(base, xr, transpose=transpose)
+    ri = ctx.simple_krylov_vec(base, xi, transpose=transpose)
+    ctx.multiaxpy(rr, 1.0, XX, [-lr, li])          # A xr - (lr xr - li xi)
+    ctx.multiaxpy(ri, 1.0, XX, [-li, -lr])         # A xi - (lr xi + li xr)
+    num = ctx.dot(rr, rr) + ctx.dot(ri, ri)
+    den = ctx.dot(xr, xr) + ctx.dot(xi, xi)
+    return float(np.sqrt(num / den))

@@ -1,0 +1,151 @@
+"""GPU tests of the drivers around the Krylov vector: Krylov-Schur
+eigenvalues (vs ARPACK on the oracle operator and the dense saddle-point
+pencil), the Newton steady state (vs the oracle's sparse-direct Newton and
+the oracle residual), the adjoint (autograd backward = A^T, dot-product test,
+d lambda / d Gr vs a central difference), and mixed precision eigenvalues."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ops
+from oracle.dense import dense_pencil_eigs
+from oracle.grid import Grid, TANH, UNIFORM
+from oracle.krylov import Oracle, dlam_dGr as ora_dlam
+from paper_1905_11601_amd import inputs
+from tests.gpu_util import base, dev, krylov_input, rel_err, setup
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::UserWarning")]
+
+
+def _match(lam, ref, k):
+    """max relative distance of each of the first k values to the nearest ref."""
+    return max(np.min(np.abs(ref - l)) / abs(ref[0]) for l in lam[:k])
+
+
+@pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
+def test_krylov_schur_matches_dense_pencil(fvk, bc):
+    from paper_1905_11601_amd.eigs import krylov_schur, ritz_residual
+    print(f"case eigs 5^3 bc={bc}", flush=True)
+    g, orc, ctx = setup((5, 5, 5), TANH, 1.5, bc)
+    U = base(g, bc)
+    lam_p = dense_pencil_eigs(g, orc.prm, U, bc)
+    v0 = dev(krylov_input(g, orc, 5000))
+    r = krylov_schur(ctx, dev(U), k=6, m=30, v0=v0, tol=1e-11)
+    assert r.converged
+    assert _match(r.lam, lam_p[:10], 6) < 1e-9
+    for q in range(len(r.lam)):
+        assert ritz_residual(ctx, dev(U), r.lam[q], r.X[q]) < 1e-9
+
+
+@pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
+def test_krylov_schur_matches_arpack_on_oracle(fvk, bc):
+    from paper_1905_11601_amd.eigs import krylov_schur
+    print(f"case eigs 10^3 bc={bc}", flush=True)
+    g, orc, ctx = setup((10, 10, 10), TANH, 1.5, bc)
+    U = base(g, bc)
+    x0 = krylov_input(g, orc, 5000)
+    lam_o, _ = orc.leading_eigs(U, k=6, ncv=40, v0=x0, tol=1e-13)
+    r = krylov_schur(ctx, dev(U), k=6, m=40, v0=dev(x0), tol=1e-11)
+    assert r.converged
+    assert _match(r.lam, lam_o, 5) < 1e-9
+
+
+def test_newton_matches_oracle_newton(fvk):
+    print("case newton 8^3", flush=True)
+    g, orc, ctx = setup((8, 8, 8), TANH, 1.5, 0, Gr=2e4)
+    U0 = torch.as_tensor(inputs.conduction_state(tuple(a.c for a in g.ax), 0))
+    ref, hist = orc.newton(U0, tol=1e-11)
+    Ug = dev(U0)
+    rep = ctx.newton_step(Ug, tol=1e-11, gmres_m=60, lin_tol=1e-12, max_newton=12)
+    print("newton report", rep, flush=True)
+    assert rep["status"] == 0 and rep["res_after"] < 1e-11
+    assert 5 <= rep["newton_its"] <= 9
+    assert rel_err(Ug, ref) < 1e-9
+
+
+def test_config0_newton_then_arnoldi_20cube(fvk):
+    """20^3 uniform grid, Pr 0.71, Gr 1e5, conducting walls: Newton from the
+    conduction state, then Krylov-Schur with Krylov dimension 40 for the 6
+    leading eigenvalues, all FP64.  Certified against the oracle: its residual
+    at the GPU steady state, and ARPACK on the oracle operator about it."""
+    from paper_1905_11601_amd.eigs import krylov_schur
+    print("case config0 20^3", flush=True)
+    g, orc, ctx = setup((20, 20, 20), UNIFORM, 0.0, 0, Gr=1e5)
+    U0 = torch.as_tensor(inputs.conduction_state(tuple(a.c for a in g.ax), 0))
+    Ug = dev(U0)
+    rep = ctx.newton_step(Ug, tol=1e-10, gmres_m=100, lin_tol=1e-11, max_newton=12)
+    print("newton report", rep, flush=True)
+    assert rep["status"] == 0 and rep["newton_its"] <= 9
+    Uc = Ug.cpu()
+    assert float(orc.residual(Uc, project=True).abs().max()) < 1e-10
+    x0 = krylov_input(g, orc, 5000)
+    r = krylov_schur(ctx, Ug, k=6, m=40, v0=dev(x0), tol=1e-10, max_restarts=400)
+    print("eigs", r.lam, "restarts", r.restarts, "nvec", r.nvec, flush=True)
+    assert r.converged
+    lam_o, _ = orc.leading_eigs(Uc, k=8, ncv=40, v0=x0, tol=1e-12)
+    assert _match(r.lam, lam_o, 6) < 1e-9
+
+
+def test_adjoint_dot_product_and_autograd(fvk):
+    from paper_1905_11601_amd.adjoint import krylov_vec
+    print("case adjoint dot test 24^3", flush=True)
+    g, orc, ctx = setup((24, 22, 26), TANH, 1.5, 1)
+    U = dev(base(g, 1))
+    worst = 0.0
+    for q in range(32):
+        x = dev(torch.as_tensor(inputs.random_fields(g.n, 3000 + q)))
+        y = dev(torch.as_tensor(inputs.random_fields(g.n, 4000 + q)))
+        Ax = ctx.simple_krylov_vec(U, x)
+        ATy = ctx.simple_krylov_vec(U, y, transpose=True)
+        a, b = ctx.dot(y, Ax), ctx.dot(ATy, x)
+        worst = max(worst, abs(a - b) / max(abs(a), abs(b)))
+    assert worst < 1e-12
+    x = dev(krylov_input(g, orc, 3000)).requires_grad_(True)
+    y = dev(torch.as_tensor(inputs.random_fields(g.n, 4000)))
+    out = krylov_vec(ctx, U, x)
+    (gx,) = torch.autograd.grad(out, x, grad_outputs=y)
+    assert rel_err(gx, ctx.simple_krylov_vec(U, y, transpose=True)) == 0.0
+
+
+def test_dlam_dGr_adjoint_vs_central_difference(fvk):
+    from paper_1905_11601_amd.adjoint import dlam_dGr, left_eigvecs
+    from paper_1905_11601_amd.eigs import krylov_schur
+    print("case dlam/dGr 8^3", flush=True)
+    Gr = 1e6
+    g, orc, ctx = setup((8, 8, 8), TANH, 1.5, 0, Gr=Gr)
+    U = dev(base(g, 0))
+    v0 = dev(krylov_input(g, orc, 5000))
+    r = krylov_schur(ctx, U, k=4, m=40, v0=v0, tol=1e-12)
+    lam0, x0 = r.lam[0], r.X[0]
+    seed = dev(torch.as_tensor(inputs.random_fields(g.n, 5001)))
+    rT, ys = left_eigvecs(ctx, U, [lam0], k=4, m=40, seed_vec=seed, tol=1e-12)
+    assert np.min(np.abs(rT.lam - np.conj(lam0))) < 1e-9 * abs(lam0)
+    d_adj = dlam_dGr(ctx, U, x0, ys[0])
+    step = 1e-4 * Gr
+    lams = []
+    for G2 in (Gr + step, Gr - step):
+        ctx.set_params(G2)
+        rr = krylov_schur(ctx, U, k=4, m=40, v0=v0, tol=1e-12, vectors=False)
+        lams.append(rr.lam[int(np.argmin(np.abs(rr.lam - lam0)))])
+    ctx.set_params(Gr)
+    d_fd = (lams[0] - lams[1]) / (2 * step)
+    print("dlam/dGr adjoint", d_adj, "fd", d_fd, flush=True)
+    assert abs(d_adj - d_fd) < 1e-6 * abs(d_fd)
+    # the same derivative from the oracle's own eigenvectors
+    d_ora = ora_dlam(orc, x0.cpu().numpy(), ys[0].cpu().numpy())
+    assert abs(d_adj - d_ora) < 1e-8 * abs(d_ora)
+
+
+def test_mixed_precision_eigenvalues(fvk):
+    from paper_1905_11601_amd.eigs import krylov_schur
+    print("case mixed eigs 16^3", flush=True)
+    g, orc, ctx = setup((16, 16, 16), TANH, 1.5, 0)
+    U = dev(base(g, 0))
+    v0 = dev(krylov_input(g, orc, 5000))
+    r64 = krylov_schur(ctx, U, k=6, m=40, v0=v0, tol=1e-11, vectors=False)
+    ctx.set_precision(1)
+    r32 = krylov_schur(ctx, U, k=6, m=40, v0=v0, tol=1e-11, vectors=False)
+    ctx.set_precision(0)
+    err = _match(r32.lam, r64.lam, 6)
+    print("mixed vs fp64 eigenvalue rel error", err, flush=True)
+    assert err < 1e-6
