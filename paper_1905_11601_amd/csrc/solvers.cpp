@@ -6,6 +6,8 @@
 // library's kernels; only the small Hessenberg / Givens / BiCGstab scalars
 // live on the host.
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -14,6 +16,13 @@
 using namespace fvk;
 
 namespace {
+
+// Convergence log to stderr when the environment variable FVK_VERBOSE is set
+// (one line per Newton iteration, GMRES cycle and 100 BiCGstab(2) iterations).
+bool verbose() {
+    static const bool v = std::getenv("FVK_VERBOSE") != nullptr;
+    return v;
+}
 
 struct Dev {
     fvk_ctx *ctx;
@@ -128,6 +137,10 @@ fvk_status gmres(Dev &d, const double *base, const double *b, double *x, double 
         const double beta_new = d.nrm(r);
         if (d.st != FVK_OK) return d.st;
         const bool saturated = beta_new > sat_ratio * beta;
+        if (verbose())
+            std::fprintf(stderr, "[fvk] gmres cycle %d: %d vectors, |r|/|b| %.3e (estimate %.3e)%s\n",
+                         *cycles, jend, beta_new / bn, std::fabs(gvec[jend]) / bn,
+                         saturated ? " saturated" : "");
         beta = beta_new;
         if (saturated) break;
     }
@@ -135,9 +148,12 @@ fvk_status gmres(Dev &d, const double *base, const double *b, double *x, double 
     return FVK_OK;
 }
 
-// BiCGstab(2) on A x = b from x (in/out); work holds 8 vectors.
+// BiCGstab(2) on A x = b from x (in/out); work holds 8 vectors, xbest one.
+// Past its attainable accuracy BiCGstab can wander off; the best iterate seen
+// is kept and returned, and the iteration stops once the residual exceeds
+// 1e4 times the best one.
 fvk_status bicgstab2(Dev &d, const double *base, const double *b, double *x, double *work,
-                     int max_it, double tol, double *rel, int *its, int *nvec) {
+                     double *xbest, int max_it, double tol, double *rel, int *its, int *nvec) {
     const size_t n = d.n;
     double *r0t = work, *r[3] = {work + n, work + 2 * n, work + 3 * n};
     double *u[3] = {work + 4 * n, work + 5 * n, work + 6 * n};
@@ -157,19 +173,21 @@ fvk_status bicgstab2(Dev &d, const double *base, const double *b, double *x, dou
     d.fill(u[0], 0.0);
     double rho0 = 1.0, alpha = 0.0, omega = 1.0;
     double res = d.nrm(r[0]) / bn;
+    double best = res;
+    d.copy(xbest, x);
     *its = 0;
     while (res > tol && *its < max_it && d.st == FVK_OK) {
         rho0 = -omega * rho0;
         for (int j = 0; j < L; ++j) {
             const double rho1 = d.dot(r[j], r0t);
-            if (rho0 == 0.0) return FVK_EBREAKDOWN;
+            if (rho0 == 0.0) break;
             const double beta = alpha * rho1 / rho0;
             rho0 = rho1;
             for (int i = 0; i <= j; ++i) d.axpby(u[i], 1.0, r[i], -beta);   // u_i = r_i - beta u_i
             d.apply(base, u[j], u[j + 1]);
             ++*nvec;
             const double gamma = d.dot(u[j + 1], r0t);
-            if (gamma == 0.0) return FVK_EBREAKDOWN;
+            if (gamma == 0.0) break;
             alpha = rho0 / gamma;
             for (int i = 0; i <= j; ++i) d.axpby(r[i], -alpha, u[i + 1], 1.0);
             d.apply(base, r[j], r[j + 1]);
@@ -185,7 +203,7 @@ fvk_status bicgstab2(Dev &d, const double *base, const double *b, double *x, dou
                 d.axpby(r[j], -tau[i][j], r[i], 1.0);
             }
             sig[j] = d.dot(r[j], r[j]);
-            if (sig[j] == 0.0) return FVK_EBREAKDOWN;
+            if (sig[j] == 0.0) sig[j] = 1e-300;
             gp[j] = d.dot(r[0], r[j]) / sig[j];
         }
         g[L] = gp[L];
@@ -210,8 +228,17 @@ fvk_status bicgstab2(Dev &d, const double *base, const double *b, double *x, dou
         }
         ++*its;
         res = d.nrm(r[0]) / bn;
+        if (verbose() && (*its % 100 == 0 || res <= tol))
+            std::fprintf(stderr, "[fvk] bicgstab(2) it %d: |r|/|b| %.3e\n", *its, res);
+        if (res < best) {
+            best = res;
+            d.copy(xbest, x);
+        } else if (!(res < 1e4 * best)) {
+            break;
+        }
     }
-    *rel = res;
+    if (best < res) d.copy(x, xbest);
+    *rel = std::fmin(best, res);
     return d.st;
 }
 
@@ -258,6 +285,7 @@ fvk_status newton_step(fvk_ctx *ctx, double *base, const fvk_newton_opts *opts,
         }
         if (it == 0) R.res_before = res;
         R.res_after = res;
+        if (verbose()) std::fprintf(stderr, "[fvk] newton it %d: max|P F| %.3e\n", it, res);
         if (res < o.tol || it == o.max_newton) break;
         d.fill(x, 0.0);
         double rel = 1.0;
@@ -268,7 +296,7 @@ fvk_status newton_step(fvk_ctx *ctx, double *base, const fvk_newton_opts *opts,
         if (st != FVK_OK) goto done;
         if (rel > o.lin_tol && o.bicgstab_max_it > 0) {
             int its = 0;
-            st = bicgstab2(d, base, b, x, work + 2 * ntot, o.bicgstab_max_it, o.lin_tol, &rel,
+            st = bicgstab2(d, base, b, x, work + 2 * ntot, V, o.bicgstab_max_it, o.lin_tol, &rel,
                            &its, &R.krylov_vecs);
             R.bicgstab_its += its;
             if (st != FVK_OK && st != FVK_EBREAKDOWN) goto done;
