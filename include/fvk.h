@@ -194,6 +194,15 @@ typedef struct {
 } fvk_newton_report;
 
 void fvk_newton_defaults(fvk_newton_opts *opts);
+/* Solve A x = b (A = the Krylov operator about `base`, eqs (11)-(13)) for b in
+ * the constraint subspace, from the initial x (device, in/out): restarted
+ * GMRES(gmres_m) until |r|/|b| < lin_tol or saturation, then BiCGstab(2) from
+ * the GMRES iterate (Sec. 3.1).  Uses opts->gmres_m, gmres_max_restarts,
+ * sat_ratio, bicgstab_max_it and lin_tol; fills the linear fields of report
+ * (lin_rel_res, lin_status, gmres_cycles, bicgstab_its, krylov_vecs).
+ * Allocates (gmres_m + 11) vectors of device workspace for the call. */
+fvk_status fvk_linear_solve(fvk_ctx *ctx, const double *base, const double *b, double *x,
+                            const fvk_newton_opts *opts, fvk_newton_report *report);
 /* Newton iteration of Sec. 3.1 (steps 1-4) on `base` in place: b = P F;
  * solve A delta = b by restarted GMRES(m) until converged or saturated, then
  * BiCGstab(2) from the GMRES iterate; base <- base - delta; repeat up to

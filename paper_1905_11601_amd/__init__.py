@@ -225,6 +225,26 @@ class Ctx:
                                               Q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                               k, self.N))
 
+    def _opts(self, opts):
+        from ._lib import NewtonOpts
+        o = NewtonOpts()
+        self.lib.fvk_newton_defaults(ctypes.byref(o))
+        for k, v in opts.items():
+            setattr(o, k, v)
+        return o
+
+    def linear_solve(self, base, b, x=None, **opts):
+        """Solve A x = b (GMRES(m) then BiCGstab(2)); returns (x, report)."""
+        from ._lib import NewtonReport
+        x = self.zeros() if x is None else x
+        o = self._opts(opts)
+        r = NewtonReport()
+        st = self.lib.fvk_linear_solve(self.h, self._vec(base, "base"), self._vec(b, "b"),
+                                       self._vec(x, "x"), ctypes.byref(o), ctypes.byref(r))
+        rep = {f: getattr(r, f) for f, _ in NewtonReport._fields_}
+        rep["status"] = st
+        return x, rep
+
     def newton_step(self, base, **opts):
         from ._lib import NewtonOpts, NewtonReport
         o = NewtonOpts()

@@ -62,6 +62,8 @@ SIGNATURES = {
                                  c_size_t]),
     "fvk_newton_defaults": (None, [P(NewtonOpts)]),
     "newton_step": (c_int, [c_void_p, c_void_p, P(NewtonOpts), P(NewtonReport)]),
+    "fvk_linear_solve": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, P(NewtonOpts),
+                                 P(NewtonReport)]),
 }
 
 _lib = None

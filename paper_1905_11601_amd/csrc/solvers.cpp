@@ -257,6 +257,58 @@ void fvk_newton_defaults(fvk_newton_opts *o) {
     o->max_newton = 12;
 }
 
+namespace {
+
+// GMRES(m) then BiCGstab(2) on A x = b; V: (m+1) vectors, work: 10 vectors.
+fvk_status linear_solve(Dev &d, const double *base, const double *b, double *x, double *V,
+                        double *work, const fvk_newton_opts &o, fvk_newton_report &R) {
+    const size_t n = d.n;
+    double rel = 1.0;
+    int cyc = 0;
+    fvk_status st = gmres(d, base, b, x, V, o.gmres_m, o.gmres_max_restarts, o.lin_tol,
+                          o.sat_ratio, &rel, &cyc, &R.krylov_vecs, work, work + n);
+    R.gmres_cycles += cyc;
+    if (st != FVK_OK) return st;
+    if (rel > o.lin_tol && o.bicgstab_max_it > 0) {
+        int its = 0;
+        st = bicgstab2(d, base, b, x, work + 2 * n, V, o.bicgstab_max_it, o.lin_tol, &rel, &its,
+                       &R.krylov_vecs);
+        R.bicgstab_its += its;
+        if (st != FVK_OK) return st;
+    }
+    R.lin_rel_res = rel;
+    R.lin_status = rel <= o.lin_tol ? FVK_OK : FVK_ENOCONV;
+    return FVK_OK;
+}
+
+}  // namespace
+
+fvk_status fvk_linear_solve(fvk_ctx *ctx, const double *base, const double *b, double *x,
+                            const fvk_newton_opts *opts, fvk_newton_report *rep) {
+    if (!ctx || !base || !b || !x) return FVK_EINVAL;
+    fvk_newton_opts o;
+    fvk_newton_defaults(&o);
+    if (opts) o = *opts;
+    if (o.gmres_m < 1 || o.gmres_m > 400) return FVK_EINVAL;
+    fvk_newton_report R;
+    std::memset(&R, 0, sizeof(R));
+    size_t ntot = 0;
+    fvk_layout(ctx, nullptr, nullptr, &ntot);
+    Dev d{ctx, ntot};
+    double *V = nullptr, *work = nullptr;
+    fvk_status st = dmalloc(ctx, &V, size_t(o.gmres_m + 1) * ntot);
+    if (st == FVK_OK) st = dmalloc(ctx, &work, 10 * ntot);
+    if (st == FVK_OK) st = linear_solve(d, base, b, x, V, work, o, R);
+    if (st == FVK_OK && R.lin_status != FVK_OK) {
+        st = FVK_ENOCONV;
+        ctx->err = "fvk_linear_solve: tolerance not reached";
+    }
+    if (V) (void)hipFree(V);
+    if (work) (void)hipFree(work);
+    if (rep) *rep = R;
+    return st;
+}
+
 fvk_status newton_step(fvk_ctx *ctx, double *base, const fvk_newton_opts *opts,
                        fvk_newton_report *rep) {
     if (!ctx || !base) return FVK_EINVAL;
@@ -288,22 +340,8 @@ fvk_status newton_step(fvk_ctx *ctx, double *base, const fvk_newton_opts *opts,
         if (verbose()) std::fprintf(stderr, "[fvk] newton it %d: max|P F| %.3e\n", it, res);
         if (res < o.tol || it == o.max_newton) break;
         d.fill(x, 0.0);
-        double rel = 1.0;
-        int cyc = 0;
-        st = gmres(d, base, b, x, V, o.gmres_m, o.gmres_max_restarts, o.lin_tol, o.sat_ratio, &rel,
-                   &cyc, &R.krylov_vecs, work, work + ntot);
-        R.gmres_cycles += cyc;
+        st = linear_solve(d, base, b, x, V, work, o, R);
         if (st != FVK_OK) goto done;
-        if (rel > o.lin_tol && o.bicgstab_max_it > 0) {
-            int its = 0;
-            st = bicgstab2(d, base, b, x, work + 2 * ntot, V, o.bicgstab_max_it, o.lin_tol, &rel,
-                           &its, &R.krylov_vecs);
-            R.bicgstab_its += its;
-            if (st != FVK_OK && st != FVK_EBREAKDOWN) goto done;
-            st = FVK_OK;
-        }
-        R.lin_rel_res = rel;
-        R.lin_status = rel <= o.lin_tol ? FVK_OK : FVK_ENOCONV;
         d.axpby(base, -1.0, x, 1.0);   // U <- U - delta
         ++R.newton_its;
     }

@@ -1,0 +1,121 @@
+"""Host drivers over the C ABI: steady states by Newton with continuation in
+the Grashof number, and the critical Grashof number (Re lambda = 0, Sec. 2 and
+eq. (10)) by a Newton iteration on Gr with the adjoint eigenvalue
+sensitivity.
+
+All vector work runs in the library (newton_step, fvk_linear_solve,
+simple_krylov_vec, arnoldi_step); these functions only sequence the calls.
+"""
+import numpy as np
+
+from .adjoint import dA_dGr_apply, _cdot, left_eigvecs
+from .eigs import krylov_schur
+
+
+def steady_state(ctx, base, Gr, Gr_start=1e3, factor=3.3, newton_opts=None, log=None):
+    """Newton iteration (newton_step) for the steady state at ``Gr``, reached by
+    continuation from ``Gr_start`` in geometric steps of at most ``factor``
+    (halved on failure).  ``base`` (device, in/out) is the starting state:
+    the conduction state, or a steady state at Gr_start.  Returns the list of
+    (Gr, newton report) of the stages."""
+    opts = dict(tol=1e-10, gmres_m=100, lin_tol=1e-10, max_newton=12)
+    opts.update(newton_opts or {})
+    stages = []
+    good = base.clone()
+    g_done = None
+    g_next = min(Gr, Gr_start)
+    step = factor
+    while True:
+        ctx.set_params(g_next)
+        rep = ctx.newton_step(base, **opts)
+        stages.append((g_next, rep))
+        if log:
+            log(f"Gr {g_next:.4g}: status {rep['status']} newton {rep['newton_its']} "
+                f"res {rep['res_after']:.2e}")
+        if rep["status"] == 0:
+            good.copy_(base)
+            g_done = g_next
+            if g_done >= Gr:
+                return stages
+            step = min(factor, step * 1.5)
+            g_next = min(Gr, g_done * step)
+        else:
+            base.copy_(good)
+            if g_done is None:
+                raise RuntimeError(f"Newton failed at the first continuation stage Gr={g_next:g}")
+            step = step ** 0.5
+            if step < 1.01:
+                raise RuntimeError(f"continuation stalled at Gr={g_done:g}")
+            g_next = min(Gr, g_done * step)
+
+
+def base_flow_sensitivity(ctx, base, lin_opts=None):
+    """U' = dU/dGr at a steady state: A U' = -P dF/dGr, where dF/dGr is the
+    residual's explicit Gr dependence (nu' Lap U, kappa' Lap Theta)."""
+    Gr, Pr = ctx.Gr, ctx.Pr
+    dnu = -0.5 * Gr ** -1.5
+    try:
+        ctx.set_coeffs(dnu, dnu / Pr, 0.0)
+        F1 = ctx.fv_residual(base)
+        ctx.set_coeffs(0.0, 0.0, 0.0)
+        F0 = ctx.fv_residual(base)
+    finally:
+        ctx.set_params(Gr, Pr)
+    ctx.axpby(F1, -1.0, F0, 1.0)              # dF/dGr
+    rhs = ctx.project(F1)
+    ctx.axpby(rhs, 0.0, rhs, -1.0)            # -P dF/dGr
+    opts = dict(lin_tol=1e-10, gmres_m=100)
+    opts.update(lin_opts or {})
+    Up, rep = ctx.linear_solve(base, rhs, **opts)
+    return Up, rep
+
+
+def total_dlam_dGr(ctx, base, x, y, Up):
+    """d lambda / d Gr along the branch of steady states:
+    y^H [ dA/dGr x + (dA/dU . U') x ] / (y^H x), with
+    (dA/dU . U') x = A(U') x - A(0) x (J is affine in the base flow)."""
+    import torch
+    parts = []
+    zero = ctx.zeros()
+    for comp in (x.real, x.imag):
+        c = comp.contiguous().reshape(ctx.shape4)
+        d1 = dA_dGr_apply(ctx, c)
+        a1 = ctx.simple_krylov_vec(Up, c)
+        a0 = ctx.simple_krylov_vec(zero, c)
+        ctx.axpby(d1, 1.0, a1, 1.0)
+        ctx.axpby(d1, -1.0, a0, 1.0)
+        parts.append(d1.reshape(-1))
+    dAx = torch.complex(parts[0], parts[1])
+    return _cdot(ctx, y.reshape(-1), dAx) / _cdot(ctx, y.reshape(-1), x.reshape(-1))
+
+
+def critical_gr(ctx, base, Gr0, v0, seed, k=4, m=40, tol=1e-10, gr_rtol=1e-7, max_it=12,
+                log=None):
+    """Newton iteration on Gr for Re lambda_lead(Gr) = 0 (the paper's critical
+    Grashof number).  ``base`` (in/out) must be a steady state at Gr0.  Each
+    iteration: Newton steady state at the current Gr (from the previous one),
+    the leading right and left eigenpairs (Krylov-Schur on A and A^T), U', and
+    Gr <- Gr - Re lambda / Re(d lambda / d Gr).  Returns a history list."""
+    hist = []
+    Gr = Gr0
+    for it in range(max_it):
+        if it > 0:
+            steady_state(ctx, base, Gr, Gr_start=Gr, factor=1.0, log=log)
+        ctx.set_params(Gr)
+        r = krylov_schur(ctx, base, k, m, v0, tol=tol)
+        lead = 0
+        lam, x = r.lam[lead], r.X[lead]
+        if lam.imag < 0 and len(r.lam) > 1 and abs(r.lam[1] - np.conj(lam)) < 1e-8 * abs(lam):
+            lam, x = r.lam[1], r.X[1]
+        _, ys = left_eigvecs(ctx, base, [lam], k, m, seed, tol=tol)
+        Up, _ = base_flow_sensitivity(ctx, base)
+        dl = total_dlam_dGr(ctx, base, x, ys[0], Up)
+        hist.append({"Gr": Gr, "lam": lam, "dlam_dGr": dl, "nvec": r.nvec})
+        if log:
+            log(f"critical Gr it {it}: Gr {Gr:.8g} lambda {lam:.6g} dlam/dGr {dl:.4g}")
+        step = -lam.real / dl.real
+        Gr = Gr + step
+        if abs(step) < gr_rtol * abs(Gr):
+            hist.append({"Gr": Gr, "converged": True})
+            break
+    return hist

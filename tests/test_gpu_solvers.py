@@ -70,14 +70,21 @@ def test_config0_newton_then_arnoldi_20cube(fvk):
     at the GPU steady state, and ARPACK on the oracle operator about it."""
     from paper_1905_11601_amd.eigs import krylov_schur
     print("case config0 20^3", flush=True)
+    from paper_1905_11601_amd.drivers import steady_state
     g, orc, ctx = setup((20, 20, 20), UNIFORM, 0.0, 0, Gr=1e5)
     U0 = torch.as_tensor(inputs.conduction_state(tuple(a.c for a in g.ax), 0))
     Ug = dev(U0)
-    rep = ctx.newton_step(Ug, tol=1e-10, gmres_m=100, lin_tol=1e-10, max_newton=12)
-    print("newton report", rep, flush=True)
-    assert rep["status"] == 0 and rep["newton_its"] <= 9
+    # Newton from the conduction state diverges at Gr = 1e5 (also in the
+    # oracle); continuation in Gr from 1e3 reaches it in a few stages
+    stages = steady_state(ctx, Ug, 1e5, Gr_start=1e3, log=lambda m: print(m, flush=True))
+    for Gr, rep in stages:
+        assert rep["status"] == 0 and rep["newton_its"] <= 9
     Uc = Ug.cpu()
     assert float(orc.residual(Uc, project=True).abs().max()) < 1e-10
+    # the steady flow keeps the three symmetries of Sec. 2 (uniform grid)
+    from tests.oracle_util import sym_base, sym_y, sym_rot, sym_c
+    for S in (sym_y, sym_rot, sym_c):
+        assert float((sym_base(g, S, Uc) - Uc).abs().max()) < 1e-9
     x0 = krylov_input(g, orc, 5000)
     r = krylov_schur(ctx, Ug, k=6, m=40, v0=dev(x0), tol=1e-10, max_restarts=400)
     print("eigs", r.lam, "restarts", r.restarts, "nvec", r.nvec, flush=True)
