@@ -9,6 +9,8 @@
 // (1 <= i_A <= n_A - 1, 1 <= i_B <= n_B for B != A); rows of the energy
 // equation are the interior cells.  Forward kernels write every stored entry
 // (0 where the operator has no row).
+#include <algorithm>
+
 #include "fvk_internal.h"
 
 namespace fvk {
@@ -173,6 +175,248 @@ __global__ __launch_bounds__(BX *BY) void k_jac(Geo g, Coefs c, int span_aa,
                         : energy_row(g, idr, pr, U, Th, nullptr, nullptr, Th, c.kappa);
     }
     yT[p] = t;
+}
+
+// ---------------------------------------------------------------- forward, tiled
+//
+// The Krylov-path Jacobian: 2.5D blocking.  A block owns a TX x TY tile of the
+// interior (i, j) plane and marches in k over a chunk of planes; planes k-1,
+// k, k+1 of all eight input fields (x: u v w T, base: U V W Theta) with a
+// one-point halo in i and j sit in an LDS ring, so every global value is
+// loaded once per block (halo aside) with coalesced row loads, and the ~70
+// neighbour reads per point come from LDS.  Every stored entry of the output
+// is written exactly once: the interior by its own thread, the wall layers by
+// the threads next to them, the k = 0 and k = nz+1 planes by the first and last
+// chunk.  Blocks are remapped so that each XCD (one L2) gets a contiguous range
+// of tiles and reuses the halo rows of its neighbours.
+
+constexpr int TX = 64, TY = 4, TWP = TX + 2, THP = TY + 2, PLANE = TWP * THP, NF = 8;
+
+struct TileAcc {
+    const double *s[3];   // planes k-1, k, k+1
+    int c;                // LDS offset of this thread's centre point
+    template <int D0, int D1, int D2>
+    __device__ __forceinline__ double at(int f) const {
+        return s[D2 + 1][f * PLANE + c + D1 * TWP + D0];
+    }
+};
+
+// offset s1 along axis a1 plus s2 along axis a2, as template arguments of at<>
+#define OFF2(a1, s1, a2, s2)                                                            \
+    ((a1) == 0 ? (s1) : 0) + ((a2) == 0 ? (s2) : 0),                                   \
+        ((a1) == 1 ? (s1) : 0) + ((a2) == 1 ? (s2) : 0),                               \
+        ((a1) == 2 ? (s1) : 0) + ((a2) == 2 ? (s2) : 0)
+#define AT2(X, f, a1, s1, a2, s2) X.template at<OFF2(a1, s1, a2, s2)>(f)
+#define AT1(X, f, a1, s1) AT2(X, f, a1, s1, a1, 0)
+
+// Grid coefficients of one axis at one index i of that axis:
+// 1/h[i], 1/h[i+1], 1/d[i], 1/d[i-1], w[i], w[i-1].  For x and y they are
+// constant along a thread's k-march and live in registers; the z set is
+// uniform across the block and reloaded per plane.
+struct AxC {
+    double ih0, ih1, id0, idm, w0, wm;
+};
+
+__device__ __forceinline__ AxC axc(const AxisDev &a, int i) {
+    return AxC{a.ih[i], a.ih[i + 1], a.id[i], a.id[i - 1], a.w[i], a.w[i - 1]};
+}
+
+// field indices in the accessor: perturbation u v w T = 0..3, base = 4..7
+template <int A, int Bt>
+__device__ __forceinline__ void jrow_tangential(const AxC *C, const TileAcc &X, double wa,
+                                                double &adv, double &lap) {
+    const AxC &cB = C[Bt];
+    const double wbp = cB.w0, wbm = cB.wm;
+    // transporting component Bt at the edges (A-face, Bt-face jb and jb-1)
+    const double Utp = (1.0 - wa) * AT1(X, 4 + Bt, A, 0) + wa * AT1(X, 4 + Bt, A, 1);
+    const double Utm = (1.0 - wa) * AT1(X, 4 + Bt, Bt, -1) + wa * AT2(X, 4 + Bt, A, 1, Bt, -1);
+    const double xtp = (1.0 - wa) * AT1(X, Bt, A, 0) + wa * AT1(X, Bt, A, 1);
+    const double xtm = (1.0 - wa) * AT1(X, Bt, Bt, -1) + wa * AT2(X, Bt, A, 1, Bt, -1);
+    // transported component A at the same edges
+    const double xc = AT1(X, A, A, 0), Uc = AT1(X, 4 + A, A, 0);
+    const double xpB = AT1(X, A, Bt, 1), xmB = AT1(X, A, Bt, -1);
+    const double UpB = AT1(X, 4 + A, Bt, 1), UmB = AT1(X, 4 + A, Bt, -1);
+    const double Uap = (1.0 - wbp) * Uc + wbp * UpB, Uam = (1.0 - wbm) * UmB + wbm * Uc;
+    const double xap = (1.0 - wbp) * xc + wbp * xpB, xam = (1.0 - wbm) * xmB + wbm * xc;
+    adv += (Utp * xap + xtp * Uap - Utm * xam - xtm * Uam) * cB.ih0;
+    lap += ((xpB - xc) * cB.id0 - (xc - xmB) * cB.idm) * cB.ih0;
+}
+
+// nu Lap x_A - N_A(U, x_A) - N_A(x, U_A) (+ b T_f for A = z) at an interior A-face
+template <int A>
+__device__ __forceinline__ double jrow_mom(const AxC *C, const TileAcc &X, double nu,
+                                           double bcoef) {
+    const AxC &cA = C[A];
+    const double xc = AT1(X, A, A, 0), xp = AT1(X, A, A, 1), xm = AT1(X, A, A, -1);
+    const double Uc = AT1(X, 4 + A, A, 0), Up = AT1(X, 4 + A, A, 1), Um = AT1(X, 4 + A, A, -1);
+    const double Ubp = 0.5 * (Uc + Up), Ubm = 0.5 * (Um + Uc);
+    const double xbp = 0.5 * (xc + xp), xbm = 0.5 * (xm + xc);
+    double adv = (Ubp * xbp - Ubm * xbm + xbp * Ubp - xbm * Ubm) * cA.id0;
+    double lap = ((xp - xc) * cA.ih1 - (xc - xm) * cA.ih0) * cA.id0;
+    const double wa = cA.w0;
+    jrow_tangential<A, (A + 1) % 3>(C, X, wa, adv, lap);
+    jrow_tangential<A, (A + 2) % 3>(C, X, wa, adv, lap);
+    double r = nu * lap - adv;
+    if (A == 2) r += bcoef * ((1.0 - wa) * AT1(X, 3, 2, 0) + wa * AT1(X, 3, 2, 1));
+    return r;
+}
+
+template <int A>
+__device__ __forceinline__ void jrow_energy_axis(const AxC *C, const TileAcc &X, double &adv,
+                                                 double &lap) {
+    const AxC &cA = C[A];
+    const double wp = cA.w0, wm = cA.wm, ih = cA.ih0;
+    const double Tc = AT1(X, 3, A, 0), Tp = AT1(X, 3, A, 1), Tm = AT1(X, 3, A, -1);
+    const double Hc = AT1(X, 7, A, 0), Hp = AT1(X, 7, A, 1), Hm = AT1(X, 7, A, -1);
+    const double Tfp = (1.0 - wp) * Tc + wp * Tp, Tfm = (1.0 - wm) * Tm + wm * Tc;
+    const double Hfp = (1.0 - wp) * Hc + wp * Hp, Hfm = (1.0 - wm) * Hm + wm * Hc;
+    adv += (AT1(X, 4 + A, A, 0) * Tfp - AT1(X, 4 + A, A, -1) * Tfm + AT1(X, A, A, 0) * Hfp -
+            AT1(X, A, A, -1) * Hfm) * ih;
+    lap += ((Tp - Tc) * cA.id0 - (Tc - Tm) * cA.idm) * ih;
+}
+
+__device__ __forceinline__ double jrow_energy(const AxC *C, const TileAcc &X, double kappa) {
+    double adv = 0.0, lap = 0.0;
+    jrow_energy_axis<0>(C, X, adv, lap);
+    jrow_energy_axis<1>(C, X, adv, lap);
+    jrow_energy_axis<2>(C, X, adv, lap);
+    return kappa * lap - adv;
+}
+
+// LDS-only workgroup barrier: orders LDS traffic without waiting for the
+// global loads (prefetch) and stores (outputs) in flight.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+constexpr int NT_T = TX * TY;
+constexpr int PER_T = (PLANE + NT_T - 1) / NT_T;   // plane entries per thread per field
+
+// global -> registers for one plane (tile + halo) of all fields.  Branch-free:
+// out-of-box entries load a clamped (valid) address and are then zeroed, so
+// all NF * PER_T loads are issued back to back.
+__device__ __forceinline__ void fetch_plane(const Geo &g, const double *const *fp, int i0, int j0,
+                                            int kk, int tid, double (&reg)[NF][PER_T]) {
+    const long base = long(kk) * g.s[2];
+#pragma unroll
+    for (int q = 0; q < PER_T; ++q) {
+        const int r = min(tid + q * NT_T, PLANE - 1);
+        const int gi = i0 + r % TWP, gj = j0 + r / TWP;
+        const bool ok = gi < g.np[0] && gj < g.np[1];
+        const long off = base + long(min(gj, g.np[1] - 1)) * g.s[1] + min(gi, g.np[0] - 1);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const double v = fp[f][off];
+            reg[f][q] = ok ? v : 0.0;
+        }
+    }
+}
+
+__device__ __forceinline__ void put_plane(double *dst, int tid, const double (&reg)[NF][PER_T]) {
+#pragma unroll
+    for (int q = 0; q < PER_T; ++q) {
+        const int r = tid + q * NT_T;
+        if (r < PLANE) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) dst[f * PLANE + r] = reg[f][q];
+        }
+    }
+}
+
+__device__ __forceinline__ void store4(const Geo &g, double *yv, double *yT, int i, int j, int k,
+                                       double u, double v, double w, double t) {
+    const long p = pos(g, i, j, k);
+    yv[p] = u;
+    yv[p + g.F] = v;
+    yv[p + 2 * g.F] = w;
+    yT[p] = t;
+}
+
+// zero the wall neighbours of interior point (i, j) in plane kk (the stored
+// entries outside the interior tile rows that this thread owns)
+__device__ __forceinline__ void wall_writes(const Geo &g, double *yv, double *yT, int i, int j,
+                                            int kk, double t_aa_lo, double t_aa_hi) {
+    const int nx = g.n[0], ny = g.n[1];
+    const int dis[3] = {0, i == 1 ? -1 : 0, i == nx ? 1 : 0};
+    const int djs[3] = {0, j == 1 ? -1 : 0, j == ny ? 1 : 0};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if ((a == 0 && b == 0) || (a > 0 && dis[a] == 0) || (b > 0 && djs[b] == 0)) continue;
+            const int di = dis[a], dj = djs[b];
+            double t = 0.0;
+            if (di == 0 && dj == -1) t = t_aa_lo;
+            if (di == 0 && dj == 1) t = t_aa_hi;
+            store4(g, yv, yT, i + di, j + dj, kk, 0.0, 0.0, 0.0, t);
+        }
+}
+
+__global__ __launch_bounds__(TX *TY, 2) void k_jac_tiled(Geo g, Coefs c, int span_aa,
+                                                         const double *__restrict__ base,
+                                                         const double *__restrict__ x,
+                                                         double *__restrict__ yv,
+                                                         double *__restrict__ yT, int kchunk) {
+    __shared__ double lds[3][NF * PLANE];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+    // XCD-aware tile order: hardware block b runs on XCD b % 8; give each XCD a
+    // contiguous range of logical tiles
+    const int nbx = gridDim.x, nby = gridDim.y, nbz = gridDim.z;
+    const int nb = nbx * nby * nbz;
+    const int b = (blockIdx.z * nby + blockIdx.y) * nbx + blockIdx.x;
+    int lb = b;
+    if ((nb % 8) == 0) lb = (b % 8) * (nb / 8) + b / 8;
+    const int bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
+    const int i0 = bx * TX, j0 = by * TY;          // halo origin (interior starts at +1)
+    const int i = i0 + 1 + tx, j = j0 + 1 + ty;
+    const int kb = 1 + bz * kchunk;
+    const int ke = min(g.n[2], kb + kchunk - 1);
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const bool act = i <= nx && j <= ny;
+    const long F = g.F;
+    const double *fp[NF] = {x, x + F, x + 2 * F, x + 3 * F, base, base + F, base + 2 * F,
+                            base + 3 * F};
+    AxC C[3];
+    C[0] = axc(g.ax[0], min(i, nx));
+    C[1] = axc(g.ax[1], min(j, ny));
+    double reg[NF][PER_T];
+    fetch_plane(g, fp, i0, j0, kb - 1, tid, reg);
+    put_plane(lds[(kb - 1) % 3], tid, reg);
+    fetch_plane(g, fp, i0, j0, kb, tid, reg);
+    put_plane(lds[kb % 3], tid, reg);
+    fetch_plane(g, fp, i0, j0, kb + 1, tid, reg);
+    TileAcc X;
+    X.c = (ty + 1) * TWP + tx + 1;
+    for (int k = kb; k <= ke; ++k) {
+        put_plane(lds[(k + 1) % 3], tid, reg);
+        lds_barrier();
+        if (k + 2 <= ke + 1) fetch_plane(g, fp, i0, j0, k + 2, tid, reg);
+        C[2] = axc(g.ax[2], k);
+        if (act) {
+            X.s[0] = lds[(k - 1) % 3];
+            X.s[1] = lds[k % 3];
+            X.s[2] = lds[(k + 1) % 3];
+            const double u = (i <= nx - 1) ? jrow_mom<0>(C, X, c.nu, c.b) : 0.0;
+            const double v = (j <= ny - 1) ? jrow_mom<1>(C, X, c.nu, c.b) : 0.0;
+            const double w = (k <= nz - 1) ? jrow_mom<2>(C, X, c.nu, c.b) : 0.0;
+            const double t = jrow_energy(C, X, c.kappa);
+            store4(g, yv, yT, i, j, k, u, v, w, t);
+            wall_writes(g, yv, yT, i, j, k, span_aa ? t : 0.0, span_aa ? t : 0.0);
+        }
+        lds_barrier();
+    }
+    if (act) {
+        if (kb == 1) {
+            store4(g, yv, yT, i, j, 0, 0.0, 0.0, 0.0, 0.0);
+            wall_writes(g, yv, yT, i, j, 0, 0.0, 0.0);
+        }
+        if (ke == nz) {
+            store4(g, yv, yT, i, j, nz + 1, 0.0, 0.0, 0.0, 0.0);
+            wall_writes(g, yv, yT, i, j, nz + 1, 0.0, 0.0);
+        }
+    }
 }
 
 // ---------------------------------------------------------------- transpose
@@ -496,7 +740,15 @@ int correct_blocks(const Geo &g) {
 
 void launch_jacvec(const Geo &g, Coefs c, int span_aa, int ext, const double *base,
                    const double *x, double *yv, double *yT, hipStream_t st) {
-    k_jac<0><<<box_grid(g), dim3(BX, BY), 0, st>>>(g, c, span_aa && ext, base, x, yv, yT);
+    // tiles of the interior plane; k split into chunks so the grid fills the
+    // chip (>= ~2 blocks per CU) while each block keeps a long k-march
+    const int nbx = (g.n[0] + TX - 1) / TX, nby = (g.n[1] + TY - 1) / TY;
+    int nchunk = (512 + nbx * nby - 1) / (nbx * nby);
+    nchunk = std::max(1, std::min(nchunk, g.n[2] / 4 > 0 ? g.n[2] / 4 : 1));
+    const int kchunk = (g.n[2] + nchunk - 1) / nchunk;
+    nchunk = (g.n[2] + kchunk - 1) / kchunk;
+    k_jac_tiled<<<dim3(nbx, nby, nchunk), dim3(TX, TY), 0, st>>>(g, c, span_aa && ext, base, x,
+                                                                  yv, yT, kchunk);
 }
 
 void launch_residual(const Geo &g, Coefs c, int span_aa, const double *base, double *F,
