@@ -64,6 +64,7 @@ void free_ws(fvk_ctx *ctx) {
     fr(w.red);
     fr(w.dev_scalars);
     fr(w.dev_counters);
+    fr(w.div_slots);
     fr(w.coef_dev);
     if (w.host_pinned) (void)hipHostFree(w.host_pinned);
     w = Workspace();
@@ -110,7 +111,6 @@ fvk_status simple_forward(fvk_ctx *ctx, double *vin, double *vout, double *p_out
     hipStream_t st = ctx->stream;
     const bool fp32 = ctx->prec == FVK_MIXED;
     const int fixed = fp32 ? ctx->mixed_passes : 1;
-    const int nred = correct_blocks(g);
     if (p_out) launch_fill(p_out, 0.0, ctx->ncell, st);
     timing_begin(ctx, FVK_STAGE_DIV);
     launch_div(g, vin, w.div, st);
@@ -120,17 +120,20 @@ fvk_status simple_forward(fvk_ctx *ctx, double *vin, double *vout, double *p_out
     double dmax = 0.0;
     while (true) {
         tpf_solve(ctx, w.div, w.phi, fp32, st);
+        const bool last_fixed = !sync && k + 1 >= fixed;
         timing_begin(ctx, FVK_STAGE_CORRECT);
         launch_correct_oop(g, src, dst, w.phi, p_out, w.div, w.red, st);
-        timing_end(ctx, FVK_STAGE_CORRECT);
-        ++k;
-        const bool last_fixed = !sync && k >= fixed;
-        launch_max_reduce(w.red, nred, w.dev_scalars, last_fixed ? w.dev_scalars + 1 : nullptr,
+        launch_max_reduce(w.red, correct_blocks(g), w.div_slots,
+                          last_fixed ? w.div_slots + 1 : nullptr,
                           last_fixed ? w.dev_counters : nullptr, ctx->simple_tol, st);
+        timing_end(ctx, FVK_STAGE_CORRECT);
         CHECK_LAUNCH(ctx);
         if (sync) {
-            fvk_status s = read_back(ctx, w.dev_scalars, &dmax, 1);
+            fvk_status s = read_back(ctx, w.div_slots, &dmax, 1);
             if (s != FVK_OK) return s;
+        }
+        ++k;
+        if (sync) {
             if (dmax < ctx->simple_tol || k >= ctx->simple_cap) break;
         } else if (k >= fixed) {
             break;
@@ -298,6 +301,7 @@ fvk_status fvk_create(fvk_ctx **out, int nx, int ny, int nz, int grid_kind, doub
     if ((st = dalloc(ctx, &w.red, w.red_len)) != FVK_OK) goto bad;
     if ((st = dalloc(ctx, &w.dev_scalars, 4096)) != FVK_OK) goto bad;
     if ((st = dalloc(ctx, &w.dev_counters, 16)) != FVK_OK) goto bad;
+    if ((st = dalloc(ctx, &w.div_slots, 4)) != FVK_OK) goto bad;
     w.coef_len = 65536;
     if ((st = dalloc(ctx, &w.coef_dev, w.coef_len)) != FVK_OK) goto bad;
     w.host_pinned_len = 65536;
@@ -334,7 +338,8 @@ fvk_status fvk_create(fvk_ctx **out, int nx, int ny, int nz, int grid_kind, doub
     }
     if (hipMemcpy(w.geo, geo.data(), geo.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(w.dev_scalars, 0, 4096 * 8) != hipSuccess ||
-        hipMemset(w.dev_counters, 0, 16 * sizeof(int)) != hipSuccess) {
+        hipMemset(w.dev_counters, 0, 16 * sizeof(int)) != hipSuccess ||
+        hipMemset(w.div_slots, 0, 4 * sizeof(double)) != hipSuccess) {
         st = fail(ctx, FVK_EHIP, "geometry upload failed");
         goto bad;
     }
@@ -518,16 +523,15 @@ fvk_status simple_krylov_vec(fvk_ctx *ctx, const double *base, const double *x, 
 
 fvk_status fvk_simple_stats(fvk_ctx *ctx, double *max_div, int *n_unconverged) {
     if (!ctx) return FVK_EINVAL;
-    double tmp[2];
-    fvk_status s = read_back(ctx, ctx->ws.dev_scalars, tmp, 2);
-    if (s != FVK_OK) return s;
-    int cnt = 0;
-    HIPCHK(ctx, hipMemcpy(&cnt, ctx->ws.dev_counters, sizeof(int), hipMemcpyDeviceToHost));
-    if (max_div) *max_div = tmp[1];
-    if (n_unconverged) *n_unconverged = cnt;
-    launch_fill(ctx->ws.dev_scalars + 1, 0.0, 1, ctx->stream);
-    HIPCHK(ctx, hipMemsetAsync(ctx->ws.dev_counters, 0, sizeof(int), ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    double m = 0.0;
+    int cnt = 0;
+    HIPCHK(ctx, hipMemcpy(&m, ctx->ws.div_slots + 1, 8, hipMemcpyDeviceToHost));
+    HIPCHK(ctx, hipMemcpy(&cnt, ctx->ws.dev_counters, sizeof(int), hipMemcpyDeviceToHost));
+    if (max_div) *max_div = m;
+    if (n_unconverged) *n_unconverged = cnt;
+    HIPCHK(ctx, hipMemset(ctx->ws.div_slots + 1, 0, 8));
+    HIPCHK(ctx, hipMemset(ctx->ws.dev_counters, 0, sizeof(int)));
     return FVK_OK;
 }
 

@@ -71,8 +71,9 @@ struct Workspace {
     size_t coef_len = 0;
     double *red = nullptr;          // reduction scratch (partials)
     size_t red_len = 0;
-    double *dev_scalars = nullptr;  // [0] max div of last pass, [1] running max (async)
-    int *dev_counters = nullptr;    // [0] async calls above tolerance
+    double *dev_scalars = nullptr;  // small device scalars (dot products, norms)
+    int *dev_counters = nullptr;    // [0] async calls above tolerance, [1] block counter
+    double *div_slots = nullptr;    // [0] max |D v| of the last pass, [1] running max (async)
     double *host_pinned = nullptr;  // pinned host staging for small reads
     size_t host_pinned_len = 0;
 };
@@ -120,6 +121,8 @@ void launch_jacvec_T(const Geo &g, Coefs c, int span_aa, int fold_ext, const dou
 void launch_residual(const Geo &g, Coefs c, int span_aa, const double *base, double *F,
                      hipStream_t st);
 void launch_div(const Geo &g, const double *v, double *div, hipStream_t st);
+// v_out = v_in - G phi (wall entries 0), p_out += phi, div_out = D v_out,
+// block maxima of |D v_out| to red[0 .. correct_blocks)
 void launch_correct_oop(const Geo &g, const double *vin, double *vout, const double *phi,
                         double *p_out, double *div_out, double *red, hipStream_t st);
 int correct_blocks(const Geo &g);

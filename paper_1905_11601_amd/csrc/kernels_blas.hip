@@ -103,18 +103,27 @@ __global__ __launch_bounds__(NT) void k_basis_rotate(double *__restrict__ V, siz
 }
 
 // slots: out[0] = max of partials; running[0] = max(running, out);
-// count_over[0] += (out >= tol)
-__global__ void k_max_reduce(const double *__restrict__ partials, int nblk, double *out,
-                             double *running, int *count_over, double tol) {
-    __shared__ double sh[NT / 64];
+// count_over[0] += (out >= tol).  One block of 1024 threads; each thread
+// issues its loads back to back (independent) before reducing.
+constexpr int NTR = 1024;
+__global__ __launch_bounds__(NTR) void k_max_reduce(const double *__restrict__ partials, int nblk,
+                                                    double *out, double *running,
+                                                    int *count_over, double tol) {
+    __shared__ double sh[NTR / 64];
     double v = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += NT) v = fmax(v, partials[b]);
+    int b = threadIdx.x;
+    for (; b + 3 * NTR < nblk; b += 4 * NTR) {
+        const double a0 = partials[b], a1 = partials[b + NTR], a2 = partials[b + 2 * NTR],
+                     a3 = partials[b + 3 * NTR];
+        v = fmax(v, fmax(fmax(a0, a1), fmax(a2, a3)));
+    }
+    for (; b < nblk; b += NTR) v = fmax(v, partials[b]);
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int k = 0; k < NT / 64; ++k) t = fmax(t, sh[k]);
+        for (int k = 0; k < NTR / 64; ++k) t = fmax(t, sh[k]);
         out[0] = t;
         if (running) running[0] = fmax(running[0], t);
         if (count_over && !(t < tol)) count_over[0] += 1;
@@ -204,7 +213,7 @@ void launch_basis_rotate(double *V, size_t ldv, int m, const double *Q_dev, int 
 
 void launch_max_reduce(const double *partials, int nblk, double *out, double *running,
                        int *count_over, double tol, hipStream_t st) {
-    k_max_reduce<<<1, NT, 0, st>>>(partials, nblk, out, running, count_over, tol);
+    k_max_reduce<<<1, NTR, 0, st>>>(partials, nblk, out, running, count_over, tol);
 }
 
 void launch_absmax(const double *x, size_t n, double *partials, int nblk, hipStream_t st) {

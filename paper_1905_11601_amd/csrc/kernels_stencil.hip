@@ -590,10 +590,13 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
     return r;
 }
 
-// v_out = v_in - G phi on interior faces (walls keep v_in), p_out += phi,
-// div_out = D v_out, block maxima of |D v_out| to red[block].
-// Each thread owns the + faces of its cell; the - faces are recomputed from
-// v_in so the kernel is race-free with v_out != v_in.
+// v_out = v_in - G phi on interior faces, p_out += phi, div_out = D v_out, and
+// max |D v_out| over the grid.  Each thread owns the + faces of its cell; the
+// - faces are recomputed from v_in so the kernel is race-free (v_out != v_in).
+// Wall, edge and padding entries of v_out are written 0 (homogeneous no-slip,
+// SIMPLE step 3) by the threads next to them, so v_out is fully defined.
+// Block maxima of |D v_out| go to red[block]; a one-block kernel reduces them
+// (per-block atomics on one address serialise in L2 and cost far more).
 __global__ __launch_bounds__(BX *BY) void k_correct(Geo g, const double *__restrict__ vin,
                                                     const double *__restrict__ phi,
                                                     double *__restrict__ vout,
@@ -605,48 +608,47 @@ __global__ __launch_bounds__(BX *BY) void k_correct(Geo g, const double *__restr
     const int j = blockIdx.y * BY + threadIdx.y + 1;
     const int k = blockIdx.z + 1;
     double dmax = 0.0;
-    if (i <= g.n[0] && j <= g.n[1] && k <= g.n[2]) {
+    const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    if (i <= nx && j <= ny && k <= nz) {
         const long p = pos(g, i, j, k);
         const long c = cidx(g, i, j, k);
         const int idx[3] = {i, j, k};
         const double ph = phi[c];
-        const long cs[3] = {1, g.n[0], long(g.n[0]) * g.n[1]};
+        const long cs[3] = {1, nx, long(nx) * ny};
         double dv = 0.0;
 #pragma unroll
         for (int A = 0; A < 3; ++A) {
             const int ia = idx[A];
             const double *vi = vin + A * g.F;
-            double vp = vi[p];
-            if (ia <= g.n[A] - 1) vp -= (phi[c + cs[A]] - ph) * g.ax[A].id[ia];
-            double vm = vi[p - g.s[A]];
-            if (ia >= 2) vm -= (ph - phi[c - cs[A]]) * g.ax[A].id[ia - 1];
+            double vp = 0.0;   // the + face: interior row, or the wall face (0)
+            if (ia <= g.n[A] - 1) vp = vi[p] - (phi[c + cs[A]] - ph) * g.ax[A].id[ia];
+            double vm = 0.0;
+            if (ia >= 2) vm = vi[p - g.s[A]] - (ph - phi[c - cs[A]]) * g.ax[A].id[ia - 1];
             vout[A * g.F + p] = vp;
             dv += (vp - vm) * g.ax[A].ih[ia];
         }
         if (p_out) p_out[c] += ph;
         if (div_out) div_out[c] = dv;
         dmax = fabs(dv);
+        // zero the velocity wall neighbours this cell owns (the stored entries
+        // with an index 0 or n+1 next to it, including edges and corners)
+        const int lo[3] = {i == 1 ? -1 : 0, j == 1 ? -1 : 0, k == 1 ? -1 : 0};
+        const int hi[3] = {i == nx ? 1 : 0, j == ny ? 1 : 0, k == nz ? 1 : 0};
+        if (lo[0] | lo[1] | lo[2] | hi[0] | hi[1] | hi[2]) {
+            for (int dk = lo[2]; dk <= hi[2]; ++dk)
+                for (int dj = lo[1]; dj <= hi[1]; ++dj)
+                    for (int di = lo[0]; di <= hi[0]; ++di) {
+                        if (di == 0 && dj == 0 && dk == 0) continue;
+                        const long q = pos(g, i + di, j + dj, k + dk);
+                        vout[q] = 0.0;
+                        vout[q + g.F] = 0.0;
+                        vout[q + 2 * g.F] = 0.0;
+                    }
+        }
     }
     const double r = block_max(dmax, sh);
     if (threadIdx.x == 0 && threadIdx.y == 0)
         red[(long(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = r;
-}
-
-// Copy the entries of v that are not interior rows' faces written by
-// k_correct (wall-normal faces, tangential wall nodes, edges, padding) from
-// v_in to v_out, zeroed (homogeneous no-slip, SIMPLE step 3).
-__global__ void k_vel_walls_zero(Geo g, double *__restrict__ vout) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.np[0] || j >= g.np[1] || k >= g.np[2]) return;
-    const long p = pos(g, i, j, k);
-#pragma unroll
-    for (int A = 0; A < 3; ++A) {
-        if (!cell_row(g, i, j, k) || (i == g.n[0] && A == 0) || (j == g.n[1] && A == 1) ||
-            (k == g.n[2] && A == 2))
-            vout[A * g.F + p] = 0.0;
-    }
 }
 
 // zero-walls copy: dst = src on interior faces, 0 elsewhere (velocity fields)
@@ -768,7 +770,6 @@ void launch_div(const Geo &g, const double *v, double *div, hipStream_t st) {
 
 void launch_correct_oop(const Geo &g, const double *vin, double *vout, const double *phi,
                         double *p_out, double *div_out, double *red, hipStream_t st) {
-    k_vel_walls_zero<<<box_grid(g), dim3(BX, BY), 0, st>>>(g, vout);
     k_correct<<<cell_grid(g), dim3(BX, BY), 0, st>>>(g, vin, phi, vout, p_out, div_out, red);
 }
 
