@@ -14,11 +14,14 @@ from .eigs import krylov_schur
 
 def steady_state(ctx, base, Gr, Gr_start=1e3, factor=3.3, newton_opts=None, log=None):
     """Newton iteration (newton_step) for the steady state at ``Gr``, reached by
-    continuation from ``Gr_start`` in geometric steps of at most ``factor``
-    (halved on failure).  ``base`` (device, in/out) is the starting state:
-    the conduction state, or a steady state at Gr_start.  Returns the list of
-    (Gr, newton report) of the stages."""
-    opts = dict(tol=1e-10, gmres_m=100, lin_tol=1e-10, max_newton=12)
+    continuation from ``Gr_start`` in geometric steps of at most ``factor``.
+    A stage that needs more than ``max_newton`` (8) iterations is rejected and
+    retried from the last converged state with a smaller step: a Newton
+    iteration that wanders far from its start can land on a different
+    (spurious, on coarse grids) branch of steady states.  ``base`` (device,
+    in/out) is the starting state: the conduction state, or a steady state at
+    Gr_start.  Returns the list of (Gr, newton report) of the stages."""
+    opts = dict(tol=1e-10, gmres_m=100, lin_tol=1e-10, max_newton=8)
     opts.update(newton_opts or {})
     stages = []
     good = base.clone()

@@ -1,0 +1,74 @@
+"""Parity at the full workload sizes: 100^3 in the launch configuration the
+throughput benchmark times (a batch of unit Krylov vectors, asynchronous
+simple_krylov_vec calls into a preallocated batch, the divergence test read
+back afterwards), and 256^3 single vectors.  The oracle computes every output
+entry; bar: relative max-norm error <= 1e-10 (FP64 and mixed precision)."""
+import pytest
+import torch
+
+from oracle.grid import TANH
+from tests.gpu_util import base, dev, krylov_input, rel_err, setup
+
+pytestmark = [pytest.mark.gpu, pytest.mark.filterwarnings("ignore::UserWarning")]
+
+TOL = 1e-10
+
+
+@pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
+def test_100cube_batch_as_benchmarked(fvk, bc):
+    print(f"case fullsize 100^3 batch bc={bc}", flush=True)
+    g, orc, ctx = setup((100, 100, 100), TANH, 1.5, bc)
+    U = base(g, bc)
+    xs = [krylov_input(g, orc, 2000 + q) for q in range(3)]
+    X = torch.stack([dev(x) for x in xs])
+    Y = torch.empty_like(X)
+    Ud = dev(U)
+    ctx.simple_stats()
+    for q in range(len(xs)):
+        ctx.simple_krylov_vec(Ud, X[q], out=Y[q])
+    dmax, nbad = ctx.simple_stats()
+    assert nbad == 0 and dmax < 1e-9
+    for q, x in enumerate(xs):
+        assert rel_err(Y[q], orc.krylov_vec(U, x)) < TOL
+    # transposed operator and mixed precision on the first vector
+    yT = ctx.simple_krylov_vec(Ud, X[0], transpose=True)
+    assert rel_err(yT, orc.krylov_vec_T(U, xs[0])) < TOL
+    ctx.set_precision(fvk.MIXED)
+    ym, passes, dm = ctx.simple_krylov_vec(Ud, X[0], info=True)
+    assert passes >= 2 and dm < 1e-9
+    assert rel_err(ym, orc.krylov_vec(U, xs[0])) < TOL
+
+
+@pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
+def test_256cube_forward(fvk, bc):
+    print(f"case fullsize 256^3 forward bc={bc}", flush=True)
+    g, orc, ctx = setup((256, 256, 256), TANH, 1.5, bc)
+    U = base(g, bc)
+    x = krylov_input(g, orc, 2000)
+    ref = orc.krylov_vec(U, x)
+    Ud, xd = dev(U), dev(x)
+    y, passes, dm = ctx.simple_krylov_vec(Ud, xd, info=True)
+    assert passes == 1 and dm < 1e-9
+    assert rel_err(y, ref) < TOL
+    del y
+    ctx.set_precision(fvk.MIXED)
+    ym, passes, dm = ctx.simple_krylov_vec(Ud, xd, info=True)
+    assert passes >= 2 and dm < 1e-9
+    assert rel_err(ym, ref) < TOL
+
+
+def test_256cube_transpose_and_dot_product(fvk):
+    print("case fullsize 256^3 transpose", flush=True)
+    g, orc, ctx = setup((256, 256, 256), TANH, 1.5, 1)
+    U = base(g, 1)
+    x = krylov_input(g, orc, 3000)
+    Ud, xd = dev(U), dev(x)
+    yT = ctx.simple_krylov_vec(Ud, xd, transpose=True)
+    assert rel_err(yT, orc.krylov_vec_T(U, x)) < TOL
+    # <y, A x> = <A^T y, x> for a second projected vector y
+    yd = dev(krylov_input(g, orc, 4000))
+    Ax = ctx.simple_krylov_vec(Ud, xd)
+    ATy = ctx.simple_krylov_vec(Ud, yd, transpose=True)
+    lhs, rhs = ctx.dot(yd, Ax), ctx.dot(ATy, xd)
+    scale = float(torch.linalg.norm(yd) * torch.linalg.norm(Ax))
+    assert abs(lhs - rhs) < 1e-14 * scale
