@@ -106,8 +106,11 @@ int tridiag_eig(int n, const double *diag, const double *off, double *lam, doubl
 
 // D_aa = D_a G_a (Neumann): tridiagonal with V D_aa symmetric, V = diag(h).
 // S = V^1/2 D_aa V^-1/2 = Q diag(lam) Q^T gives E = V^-1/2 Q, E^-1 = Q^T V^1/2.
-// Eigenvalues sorted descending; the constant mode (lam = 0, E[:,0] = 1,
-// E^-1[0,:] = h) is set exactly.
+// Eigenvalues sorted descending.  The null vector of S is known in closed
+// form, q0 = V^1/2 1 / |V^1/2 1|; it replaces the computed one and the other
+// eigenvectors are made orthogonal to it.  (Overwriting only column 0 of E and
+// row 0 of E^-1 would leave E^-1 E - I of the size of the eigenvector error,
+// ~ eps |S| / |lam_1|, which the three-dimensional solve then amplifies.)
 void neumann_eig(const AxisHost &a, Eig1D &e) {
     const int n = a.n;
     std::vector<double> diag(n), off(std::max(n - 1, 1), 0.0);
@@ -123,29 +126,43 @@ void neumann_eig(const AxisHost &a, Eig1D &e) {
     std::vector<int> order(n);
     std::iota(order.begin(), order.end(), 0);
     std::sort(order.begin(), order.end(), [&](int p, int q) { return lam[p] > lam[q]; });
+    std::vector<double> sh(n), q0(n), col(n);
+    double len = 0.0;
+    for (int i = 0; i < n; ++i) {
+        sh[i] = std::sqrt(a.h[i + 1]);
+        len += a.h[i + 1];
+    }
+    const double rl = 1.0 / std::sqrt(len);
+    for (int i = 0; i < n; ++i) q0[i] = sh[i] * rl;
     e.n = n;
     e.lam.assign(n, 0.0);
     e.E.assign(size_t(n) * n, 0.0);
     e.Einv.assign(size_t(n) * n, 0.0);
     for (int q = 0; q < n; ++q) {
-        int src = order[q];
-        e.lam[q] = lam[src];
-        // fix the sign so the largest-magnitude component is positive
-        double big = 0.0;
-        for (int i = 0; i < n; ++i)
-            if (std::fabs(Q[i * n + src]) > std::fabs(big)) big = Q[i * n + src];
-        double sg = big < 0 ? -1.0 : 1.0;
-        for (int i = 0; i < n; ++i) {
-            double qv = sg * Q[i * n + src];
-            double sh = std::sqrt(a.h[i + 1]);
-            e.E[size_t(i) * n + q] = qv / sh;
-            e.Einv[size_t(q) * n + i] = qv * sh;
+        const int src = order[q];
+        e.lam[q] = q == 0 ? 0.0 : lam[src];
+        if (q == 0) {
+            col = q0;
+        } else {
+            for (int i = 0; i < n; ++i) col[i] = Q[size_t(i) * n + src];
+            double dot = 0.0;
+            for (int i = 0; i < n; ++i) dot += q0[i] * col[i];
+            double nrm = 0.0;
+            for (int i = 0; i < n; ++i) {
+                col[i] -= dot * q0[i];
+                nrm += col[i] * col[i];
+            }
+            // fix the sign so the largest-magnitude component is positive
+            double big = 0.0;
+            for (int i = 0; i < n; ++i)
+                if (std::fabs(col[i]) > std::fabs(big)) big = col[i];
+            const double sc = (big < 0 ? -1.0 : 1.0) / std::sqrt(nrm);
+            for (int i = 0; i < n; ++i) col[i] *= sc;
         }
-    }
-    e.lam[0] = 0.0;
-    for (int i = 0; i < n; ++i) {
-        e.E[size_t(i) * n + 0] = 1.0;
-        e.Einv[size_t(0) * n + i] = a.h[i + 1];
+        for (int i = 0; i < n; ++i) {
+            e.E[size_t(i) * n + q] = col[i] / sh[i];
+            e.Einv[size_t(q) * n + i] = col[i] * sh[i];
+        }
     }
 }
 

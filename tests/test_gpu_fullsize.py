@@ -6,6 +6,7 @@ entry; bar: relative max-norm error <= 1e-10 (FP64 and mixed precision)."""
 import pytest
 import torch
 
+from oracle import ops
 from oracle.grid import TANH
 from tests.gpu_util import base, dev, krylov_input, rel_err, setup
 
@@ -50,7 +51,11 @@ def test_256cube_forward(fvk, bc):
     y, passes, dm = ctx.simple_krylov_vec(Ud, xd, info=True)
     assert passes == 1 and dm < 1e-9
     assert rel_err(y, ref) < TOL
-    del y
+    # one FP64 pass leaves a divergence at the oracle's rounding level (a few
+    # 1e-12 here), evaluated independently of the library's own reduction
+    yc = y.cpu()
+    assert float(ops.div(g, [yc[0], yc[1], yc[2]]).abs().max()) < 1e-10
+    del y, yc
     ctx.set_precision(fvk.MIXED)
     ym, passes, dm = ctx.simple_krylov_vec(Ud, xd, info=True)
     assert passes >= 2 and dm < 1e-9
