@@ -77,8 +77,10 @@ def test_config0_newton_then_arnoldi_20cube(fvk):
     # Newton from the conduction state diverges at Gr = 1e5 (also in the
     # oracle); continuation in Gr from 1e3 reaches it in a few stages
     stages = steady_state(ctx, Ug, 1e5, Gr_start=1e3, log=lambda m: print(m, flush=True))
-    assert all(rep["status"] == 0 for _, rep in stages)
-    assert stages[-1][0] == 1e5 and stages[-1][1]["newton_its"] <= 9
+    # a stage that fails (more than 8 Newton iterations) is retried with a
+    # smaller step; the last stage is the target
+    assert stages[-1][0] == 1e5 and stages[-1][1]["status"] == 0
+    assert stages[-1][1]["newton_its"] <= 8
     Uc = Ug.cpu()
     assert float(orc.residual(Uc, project=True).abs().max()) < 1e-10
     # the steady flow keeps the three symmetries of Sec. 2 (uniform grid)
