@@ -200,13 +200,22 @@ void fvk_newton_defaults(fvk_newton_opts *opts);
  * the GMRES iterate (Sec. 3.1).  Uses opts->gmres_m, gmres_max_restarts,
  * sat_ratio, bicgstab_max_it and lin_tol; fills the linear fields of report
  * (lin_rel_res, lin_status, gmres_cycles, bicgstab_its, krylov_vecs).
+ * The solution is returned projected onto the constraint subspace (one
+ * fvk_project), which removes the gradient fields that rounding feeds into
+ * the Krylov iterates.  BiCGstab(2) keeps its best iterate and stops when the
+ * residual grows 1e4-fold over it or improves by less than 10% in 250
+ * iterations.  Returns FVK_ENOCONV if lin_tol is not reached.
  * Allocates (gmres_m + 11) vectors of device workspace for the call. */
 fvk_status fvk_linear_solve(fvk_ctx *ctx, const double *base, const double *b, double *x,
                             const fvk_newton_opts *opts, fvk_newton_report *report);
 /* Newton iteration of Sec. 3.1 (steps 1-4) on `base` in place: b = P F;
  * solve A delta = b by restarted GMRES(m) until converged or saturated, then
- * BiCGstab(2) from the GMRES iterate; base <- base - delta; repeat up to
- * max_newton times or until max |P F| < tol.  report may be NULL. */
+ * BiCGstab(2) from the GMRES iterate; base <- base - P delta (the correction
+ * projected onto the constraint subspace, so D U stays at rounding level);
+ * repeat up to max_newton times or until max |P F| < tol.  A linear solve that
+ * misses lin_tol does not stop the iteration (its state is in the report);
+ * returns FVK_ENOCONV if max |P F| >= tol after max_newton iterations.
+ * report may be NULL. */
 fvk_status newton_step(fvk_ctx *ctx, double *base, const fvk_newton_opts *opts,
                        fvk_newton_report *report);
 

@@ -124,7 +124,9 @@ class Oracle:
         return F
 
     # ---- numpy adaptors ----------------------------------------------------
-    def _op(self, base, transpose=False):
+    def _op(self, base, transpose=False, sigma=0.0):
+        """A (or A^T) as a scipy operator; sigma > 0 gives
+        B = A - sigma (I - P) (or its transpose), see ``leading_eigs``."""
         n = int(np.prod(self.shape4))
 
         def mv(v):
@@ -133,14 +135,27 @@ class Oracle:
                 return mv(v.real) + 1j * mv(v.imag)
             t = torch.as_tensor(v.reshape(self.shape4), dtype=DT)
             r = self.krylov_vec_T(base, t) if transpose else self.krylov_vec(base, t)
+            if sigma:
+                Pt = self.project_T(t) if transpose else self.project(t)
+                r = r - sigma * (t - Pt)
             return r.reshape(-1).numpy()
 
         return spla.LinearOperator((n, n), matvec=mv, dtype=np.float64)
 
-    def leading_eigs(self, base, k, ncv, v0, tol=1e-12, transpose=False, maxiter=None):
+    def leading_eigs(self, base, k, ncv, v0, tol=1e-12, transpose=False, maxiter=None,
+                     sigma=100.0):
         """k eigenvalues of largest real part (ARPACK), sorted by (-Re, -Im).
-        v0 must lie in the range of the operator (e.g. a projected vector)."""
-        op = self._op(base, transpose)
+        v0 must lie in the range of the operator (e.g. a projected vector).
+
+        Eq. (10) lives on the subspace S = range(P) (divergence-free, homogeneous
+        boundary conditions).  On whole stored arrays A = P J has, besides the
+        spectrum on S, the eigenvalue 0 on the complement ker(P) (A maps
+        everything into S).  ARPACK runs on B = A - sigma (I - P): in the
+        splitting S + ker(P), B is block triangular with the blocks A|S and
+        -sigma I, so its spectrum is that of eq. (10) plus -sigma, far to the
+        left of the wanted eigenvalues (sigma = 100 by default).  The transposed
+        problem uses B^T = A^T - sigma (I - P^T)."""
+        op = self._op(base, transpose, sigma)
         lam, X = spla.eigs(op, k=k, which='LR', ncv=ncv, v0=np.asarray(v0).reshape(-1),
                            tol=tol, maxiter=maxiter)
         order = eig_order(lam)

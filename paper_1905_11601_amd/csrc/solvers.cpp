@@ -151,7 +151,8 @@ fvk_status gmres(Dev &d, const double *base, const double *b, double *x, double 
 // BiCGstab(2) on A x = b from x (in/out); work holds 8 vectors, xbest one.
 // Past its attainable accuracy BiCGstab can wander off; the best iterate seen
 // is kept and returned, and the iteration stops once the residual exceeds
-// 1e4 times the best one.
+// 1e4 times the best one, or when the best residual has improved by less than
+// 10% over the last 250 iterations.
 fvk_status bicgstab2(Dev &d, const double *base, const double *b, double *x, double *work,
                      double *xbest, int max_it, double tol, double *rel, int *its, int *nvec) {
     const size_t n = d.n;
@@ -173,7 +174,7 @@ fvk_status bicgstab2(Dev &d, const double *base, const double *b, double *x, dou
     d.fill(u[0], 0.0);
     double rho0 = 1.0, alpha = 0.0, omega = 1.0;
     double res = d.nrm(r[0]) / bn;
-    double best = res;
+    double best = res, best_mark = res;
     d.copy(xbest, x);
     *its = 0;
     while (res > tol && *its < max_it && d.st == FVK_OK) {
@@ -235,6 +236,10 @@ fvk_status bicgstab2(Dev &d, const double *base, const double *b, double *x, dou
             d.copy(xbest, x);
         } else if (!(res < 1e4 * best)) {
             break;
+        }
+        if (*its % 250 == 0) {
+            if (best > 0.9 * best_mark) break;
+            best_mark = best;
         }
     }
     if (best < res) d.copy(x, xbest);
@@ -299,6 +304,10 @@ fvk_status fvk_linear_solve(fvk_ctx *ctx, const double *base, const double *b, d
     fvk_status st = dmalloc(ctx, &V, size_t(o.gmres_m + 1) * ntot);
     if (st == FVK_OK) st = dmalloc(ctx, &work, 10 * ntot);
     if (st == FVK_OK) st = linear_solve(d, base, b, x, V, work, o, R);
+    if (st == FVK_OK) {   // return the solution in S (see newton_step)
+        st = fvk_project(ctx, x, work, 0);
+        if (st == FVK_OK) d.copy(x, work);
+    }
     if (st == FVK_OK && R.lin_status != FVK_OK) {
         st = FVK_ENOCONV;
         ctx->err = "fvk_linear_solve: tolerance not reached";
@@ -342,7 +351,15 @@ fvk_status newton_step(fvk_ctx *ctx, double *base, const fvk_newton_opts *opts,
         d.fill(x, 0.0);
         st = linear_solve(d, base, b, x, V, work, o, R);
         if (st != FVK_OK) goto done;
-        d.axpby(base, -1.0, x, 1.0);   // U <- U - delta
+        // delta belongs to the constraint subspace S (divergence-free,
+        // homogeneous boundary values).  Iterations run past their attainable
+        // accuracy pick up gradient fields from the rounding of the Poisson
+        // solves, amplified by large coefficients, and the rest of delta then
+        // compensates for them in A delta; without this projection they would
+        // accumulate in U, giving a state with P F = 0 but D U != 0.
+        st = fvk_project(ctx, x, work, 0);
+        if (st != FVK_OK) goto done;
+        d.axpby(base, -1.0, work, 1.0);   // U <- U - delta
         ++R.newton_its;
     }
     if (R.res_after >= o.tol) {

@@ -11,16 +11,30 @@ Rayleigh quotient is handled on the host (real Schur form, scipy).
 Convergence: a Ritz pair (theta, V x) is accepted when the residual
 || A V x - theta V x || / || V x || = |b^T x| is below ``tol`` (the paper
 monitors || J X - lambda X || / || X || < 1e-10 after convergence).
+
+Null space of the stored-array operator: eq. (10) is posed on the subspace S
+of divergence-free velocities and temperatures satisfying the homogeneous
+boundary conditions; A acts on whole stored arrays and maps them into S, so it
+also has the eigenvalue 0 with the multiplicity of the complement of S.  A
+start vector in S keeps the Krylov space in S only up to rounding, and when
+the wanted (rightmost) physical eigenvalues all have negative real part the
+filter of the restarts amplifies those rounding components until Ritz values
+~1e-12 appear.  Ritz values with |theta| <= null_tol * max|theta| are
+therefore treated as unwanted: never reported, and purged at every restart.
 """
 import numpy as np
 import scipy.linalg as sla
 
 
-def _order(lam):
+def _order(lam, null_tol=0.0):
+    """Indices by decreasing real part (rounded to 1e-9 of the spectral
+    radius, so conjugate pairs tie), then decreasing imaginary part; values
+    in the null cluster (|lam| <= null_tol * max|lam|) go last."""
     lam = np.asarray(lam)
     scale = max(float(np.max(np.abs(lam))), 1e-300) if lam.size else 1.0
     re = np.round(lam.real / (1e-9 * scale))
-    return np.lexsort((-lam.imag, -re))
+    null = np.abs(lam) <= null_tol * scale
+    return np.lexsort((-lam.imag, -re, null))
 
 
 class EigResult:
@@ -30,7 +44,7 @@ class EigResult:
 
 
 def krylov_schur(ctx, base, k, m, v0, tol=1e-10, max_restarts=200, transpose=False,
-                 vectors=True, log=None):
+                 vectors=True, log=None, null_tol=1e-9):
     """k rightmost eigenvalues (largest real part) of A (transpose: A^T).
 
     v0: (N,) or ctx.shape4 float64 CUDA tensor (start vector; for A it should
@@ -58,25 +72,30 @@ def krylov_schur(ctx, base, k, m, v0, tol=1e-10, max_restarts=200, transpose=Fal
                 raise RuntimeError("Arnoldi breakdown (invariant subspace)")
         Hm = H[:m, :m]
         b = H[m, :m].copy()
-        evals = np.linalg.eigvals(Hm)
-        order = _order(evals)
-        evals = evals[order]
         # residuals of the k wanted Ritz pairs: |b^T x| for unit eigenvectors x
         w, Xh = np.linalg.eig(Hm)
-        o2 = _order(w)
+        o2 = _order(w, null_tol)
         w, Xh = w[o2], Xh[:, o2]
         Xh = Xh / np.linalg.norm(Xh, axis=0, keepdims=True)
         res = np.abs(b @ Xh)
-        lam = w
-        nconv = int(np.sum(res[:k] < tol))
+        null_thr = null_tol * max(float(np.abs(w).max()), 1e-300)
+        nwant = int(np.sum(np.abs(w) > null_thr))
+        lam = w[:nwant]
+        res = res[:nwant]
+        Xh = Xh[:, :nwant]
+        nconv = int(np.sum(res[:k] < tol)) if nwant >= k else 0
         if log:
-            log(f"restart {restart}: nvec {nvec}, lead {w[0]:.10g}, res {res[:k].max():.2e}")
+            log(f"restart {restart}: nvec {nvec}, lead {w[0]:.10g}, res {res[:k].max():.2e}"
+                f", purged {m - nwant}")
         if nconv >= k or restart == max_restarts:
             break
         # Krylov-Schur truncation: keep the `kept` rightmost Ritz values
-        thr = evals[kept - 1].real
-        scale = 1e-12 * max(1.0, np.abs(evals).max())
-        S, Q, sdim = sla.schur(Hm, output='real', sort=lambda re, im: re >= thr - scale)
+        # outside the null cluster
+        kk_keep = max(1, min(kept, nwant))
+        thr = w[kk_keep - 1].real
+        scale = 1e-12 * max(1.0, np.abs(w).max())
+        S, Q, sdim = sla.schur(Hm, output='real',
+                               sort=lambda re, im: re >= thr - scale and np.hypot(re, im) > null_thr)
         p = int(sdim)
         if p >= m or p == 0:
             p = kept
@@ -85,7 +104,7 @@ def krylov_schur(ctx, base, k, m, v0, tol=1e-10, max_restarts=200, transpose=Fal
         H[:] = 0.0
         H[:p, :p] = S[:p, :p]
         H[p, :p] = b @ Q[:, :p]
-    converged = bool(np.all(res[:k] < tol))
+    converged = bool(len(res) >= k and np.all(res[:k] < tol))
     kk = k
     # keep both members of a conjugate pair cut at position k
     if kk < len(lam) and lam[kk - 1].imag != 0 and abs(lam[kk] - np.conj(lam[kk - 1])) <= \
