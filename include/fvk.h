@@ -210,7 +210,8 @@ fvk_status fvk_linear_solve(fvk_ctx *ctx, const double *base, const double *b, d
                             const fvk_newton_opts *opts, fvk_newton_report *report);
 /* Newton iteration of Sec. 3.1 (steps 1-4) on `base` in place: b = P F;
  * solve A delta = b by restarted GMRES(m) until converged or saturated, then
- * BiCGstab(2) from the GMRES iterate; base <- base - P delta (the correction
+ * BiCGstab(2) from the GMRES iterate, each linear solve to |r| <
+ * max(lin_tol |b|, 0.01 tol) (Euclidean norms); base <- base - P delta (the correction
  * projected onto the constraint subspace, so D U stays at rounding level);
  * repeat up to max_newton times or until max |P F| < tol.  A linear solve that
  * misses lin_tol does not stop the iteration (its state is in the report);
