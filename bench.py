@@ -14,8 +14,20 @@ the dominant kernel (timed live with HIP events on the library's stream) and
 a CPU baseline of the oracle on a bounded sample of the same workload.
 
 Usage: python bench.py [--steps K] [--warmup W] [--n N] [--nvec M]
-       [--no-cpu-baseline] [--extra]
+       [--no-cpu-baseline] [--no-extra]
+       python bench.py --copy-calibration          (a 2 GiB device copy, for
+                                                    rocprofv3 --pmc scaling)
+       python bench.py --ingest-pmc FETCH WRITE CFETCH CWRITE
+           reads four rocprofv3 --pmc output folders (FETCH_SIZE and
+           WRITE_SIZE of a bench run, then of the copy calibration) and
+           writes profiles/traffic.json: HBM bytes per launch of the
+           dominant kernel, scaled so the copy reads and writes exactly its
+           size, tagged with a hash of the kernel source (a later edit of
+           the source makes the entry stale and bench.py reports null).
 """
+import csv
+import glob
+import hashlib
 import argparse
 import json
 import os
@@ -28,6 +40,11 @@ sys.path.insert(0, ROOT)
 METRIC = ("Krylov vectors/s at 100^3 & 256^3 (FP64 vs mixed+adjoint) at stated "
           "λ error")
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+COPY_BYTES = 1 << 31         # copy calibration: 2 GiB read + 2 GiB written
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+# the dominant kernel of the timed step (the TPF axis transform) and its source
+DOMINANT = "k_axis_gemm"
+DOMINANT_SRC = os.path.join(ROOT, "paper_1905_11601_amd", "csrc", "kernels_tpf.hip")
 FP64_PEAK_TFS = 78.6         # MI355X dense FP64 (vector and matrix)
 FP32_PEAK_TFS = 157.3        # MI355X dense FP32 matrix
 
@@ -53,6 +70,70 @@ def stencil_bytes_per_point():
     # jacvec: reads base (4 fields) + x (4 fields), writes the momentum
     # predictor (3 fields) + projected T (1 field), every stored point, FP64
     return (8 + 4) * 8
+
+
+def source_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def copy_calibration():
+    import torch
+    n = COPY_BYTES // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 3}))
+
+
+def _pmc_rows(folder, counter, name_part):
+    """Per-dispatch values (bytes) of `counter` for kernels whose name
+    contains name_part, from a rocprofv3 --pmc csv folder (values in KiB)."""
+    out = []
+    for path in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row["Counter_Name"] == counter and name_part in row["Kernel_Name"]:
+                    out.append(float(row["Counter_Value"]) * 1024.0)
+    return out
+
+
+def ingest_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, n):
+    fetch = _pmc_rows(fetch_dir, "FETCH_SIZE", DOMINANT)
+    write = _pmc_rows(write_dir, "WRITE_SIZE", DOMINANT)
+    # the copy is the largest dispatch of the calibration run
+    cf = max(_pmc_rows(cfetch_dir, "FETCH_SIZE", ""))
+    cw = max(_pmc_rows(cwrite_dir, "WRITE_SIZE", ""))
+    if not fetch or not write:
+        raise SystemExit(f"no {DOMINANT} dispatches in the pmc folders")
+    kf, kw = COPY_BYTES / cf, COPY_BYTES / cw
+    f_avg, w_avg = sum(fetch) / len(fetch), sum(write) / len(write)
+    rec = {"kernel": DOMINANT, "grid": n, "source": os.path.relpath(DOMINANT_SRC, ROOT),
+           "source_sha256": source_hash(DOMINANT_SRC),
+           "dispatches": [len(fetch), len(write)],
+           "fetch_bytes_raw": f_avg, "write_bytes_raw": w_avg,
+           "copy_fetch_bytes_raw": cf, "copy_write_bytes_raw": cw,
+           "fetch_scale": kf, "write_scale": kw,
+           "traffic_bytes_per_launch": f_avg * kf + w_avg * kw,
+           "algorithmic_bytes_per_launch": 2 * 8 * n ** 3}
+    with open(TRAFFIC_JSON, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
+def traffic_entry(n):
+    """Measured HBM bytes per launch of the dominant kernel, or None when no
+    measurement matches this grid and the current kernel source."""
+    try:
+        with open(TRAFFIC_JSON) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("grid") != n or rec.get("source_sha256") != source_hash(DOMINANT_SRC):
+        return None
+    return rec["traffic_bytes_per_launch"]
 
 
 def cpu_baseline(n, nvec_sample):
@@ -93,9 +174,17 @@ def main():
     ap.add_argument("--nvec", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=64)
-    ap.add_argument("--extra", action="store_true",
-                    help="also report mixed-precision, adjoint and Arnoldi-step rates")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the mixed-precision, adjoint and Arnoldi-step rates")
+    ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--ingest-pmc", nargs=4, metavar="DIR")
     args = ap.parse_args()
+    if args.ingest_pmc:
+        ingest_pmc(*args.ingest_pmc, n=args.n)
+        return
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design note, not an implementation", file=sys.stderr)
@@ -162,9 +251,11 @@ def main():
     if dominant == "transform":
         flops = 2.0 * n * ncell                   # one axis transform: 2 N flops per cell
         achieved = flops / (per["transform"] * 1e-3) / 1e12
-        roof = {"kernel": "k_axis (TPF axis transform, FP64 MFMA)", "bound": "mfma",
+        roof = {"kernel": "k_axis_gemm (TPF axis transform, FP64 MFMA)", "bound": "mfma",
                 "achieved": achieved, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
-                "frac": achieved / FP64_PEAK_TFS, "traffic": None,
+                "frac": achieved / FP64_PEAK_TFS, "traffic": traffic_entry(n),
+                "traffic_unit": "bytes per launch",
+                "algorithmic_bytes_per_launch": 2 * 8 * ncell,
                 "per_launch_us": per["transform"] * 1e3}
     else:
         bytes_per = {"jacvec": stencil_bytes_per_point() * npts,
@@ -197,7 +288,8 @@ def main():
         "roofline": roof,
         "wall_s": wall,
     }
-    if args.extra:
+    if not args.no_extra:
+        log("extra rates")
         out["extra"] = extra_rates(fvk, torch, runs, args)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")

@@ -146,12 +146,13 @@ fvk_status arnoldi_step(fvk_ctx *ctx, const double *base, double *V, size_t ldv,
 /* Stages of the Krylov-vector path timed with HIP events on the context's
  * stream when tracing is on: the Jacobian stencil (forward or transposed,
  * including the fused temperature projection), the divergence of the momentum
- * predictor, one axis transform of the TPF Poisson solve (six per solve), the
- * velocity correction with its fused divergence check, and the Gram-Schmidt
- * kernels of arnoldi_step. */
+ * predictor, the axis transforms of the TPF Poisson solve (one event pair
+ * around the six back-to-back launches of a solve, counted as six launches),
+ * the velocity correction with its fused divergence check, and the
+ * Gram-Schmidt kernels of arnoldi_step. */
 enum { FVK_STAGE_JACVEC = 0, FVK_STAGE_DIV = 1, FVK_STAGE_TRANSFORM = 2, FVK_STAGE_CORRECT = 3,
        FVK_STAGE_ORTHO = 4, FVK_NSTAGES = 5 };
-/* mask: bit s enables stage s (0 = off).  Each enabled launch records two
+/* mask: bit s enables stage s (0 = off).  Each timed stage records two
  * events (a few microseconds of queue overhead each). */
 fvk_status fvk_set_timing(fvk_ctx *ctx, int mask);
 /* Synchronises, returns accumulated milliseconds and launch counts per stage

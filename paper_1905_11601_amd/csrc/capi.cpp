@@ -180,7 +180,7 @@ static void timing_harvest(fvk_ctx *ctx) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, t.ev[2 * q], t.ev[2 * q + 1]) == hipSuccess) {
             t.ms[t.stage[q]] += ms;
-            t.count[t.stage[q]] += 1;
+            t.count[t.stage[q]] += t.launches[q];
         }
     }
     t.used = 0;
@@ -194,10 +194,11 @@ void timing_begin(fvk_ctx *ctx, int stage) {
     t.stage[t.used] = stage;
 }
 
-void timing_end(fvk_ctx *ctx, int stage) {
+void timing_end(fvk_ctx *ctx, int stage, int launches) {
     Timing &t = ctx->tm;
     if (!(t.mask & (1 << stage))) return;
     (void)hipEventRecord(t.ev[2 * t.used + 1], ctx->stream);
+    t.launches[t.used] = launches;
     ++t.used;
 }
 
@@ -211,6 +212,7 @@ fvk_status fvk_set_timing(fvk_ctx *ctx, int mask) {
     if (mask && t.ev.empty()) {
         t.ev.resize(2 * kTimingPairs);
         t.stage.resize(kTimingPairs);
+        t.launches.resize(kTimingPairs);
         for (auto &e : t.ev) HIPCHK(ctx, hipEventCreate(&e));
     }
     timing_harvest(ctx);

@@ -53,6 +53,7 @@ struct Timing {
     int mask = 0;
     std::vector<hipEvent_t> ev;          // pool, pairs (start, stop)
     std::vector<int> stage;              // stage of each recorded pair
+    std::vector<int> launches;           // kernel launches inside each pair
     size_t used = 0;                     // pairs recorded since the last harvest
     double ms[8] = {0};
     int count[8] = {0};
@@ -105,7 +106,7 @@ namespace fvk {
 
 // ---- tracing (capi.cpp): bracket one launch of `stage` with events
 void timing_begin(fvk_ctx *ctx, int stage);
-void timing_end(fvk_ctx *ctx, int stage);
+void timing_end(fvk_ctx *ctx, int stage, int launches = 1);
 
 // ---- host utilities (eig.cpp)
 void build_axis(AxisHost &a, int n, int kind, double s);

@@ -468,13 +468,6 @@ void run_axis(const Tc *M, const AxisView &v, const Tin *X, Tout *Y, const Tc *l
     k_axis<Tc, Tin, Tout, CONTIG, SCALE><<<grid, NT, 0, st>>>(M, v, X, Y, lR, l0, l1);
 }
 
-template <typename Tc, typename Tin, typename Tout, bool CONTIG, bool SCALE>
-void timed_axis(fvk_ctx *ctx, const Tc *M, const AxisView &v, const Tin *X, Tout *Y,
-                const Tc *lR, const Tc *l0, const Tc *l1, hipStream_t st) {
-    timing_begin(ctx, FVK_STAGE_TRANSFORM);
-    run_axis<Tc, Tin, Tout, CONTIG, SCALE>(M, v, X, Y, lR, l0, l1, st);
-    timing_end(ctx, FVK_STAGE_TRANSFORM);
-}
 
 template <typename Tc>
 void tpf_typed(fvk_ctx *ctx, const double *b, double *phi, const Tc *const *E,
@@ -488,12 +481,15 @@ void tpf_typed(fvk_ctx *ctx, const double *b, double *phi, const Tc *const *E,
     const AxisView vz{nz, pl, nx, 1, nx, nx * ny};
     Tc *t0 = static_cast<Tc *>(ctx->ws.tb0);
     Tc *t1 = static_cast<Tc *>(ctx->ws.tb1);
-    timed_axis<Tc, double, Tc, true, false>(ctx, Einv[0], vx, b, t0, nullptr, nullptr, nullptr, st);
-    timed_axis<Tc, Tc, Tc, false, false>(ctx, Einv[1], vy, t0, t1, nullptr, nullptr, nullptr, st);
-    timed_axis<Tc, Tc, Tc, false, true>(ctx, Einv[2], vz, t1, t0, lam[2], lam[0], lam[1], st);
-    timed_axis<Tc, Tc, Tc, false, false>(ctx, E[2], vz, t0, t1, nullptr, nullptr, nullptr, st);
-    timed_axis<Tc, Tc, Tc, false, false>(ctx, E[1], vy, t1, t0, nullptr, nullptr, nullptr, st);
-    timed_axis<Tc, Tc, double, true, false>(ctx, E[0], vx, t0, phi, nullptr, nullptr, nullptr, st);
+    // one event pair around the six back-to-back launches
+    timing_begin(ctx, FVK_STAGE_TRANSFORM);
+    run_axis<Tc, double, Tc, true, false>(Einv[0], vx, b, t0, nullptr, nullptr, nullptr, st);
+    run_axis<Tc, Tc, Tc, false, false>(Einv[1], vy, t0, t1, nullptr, nullptr, nullptr, st);
+    run_axis<Tc, Tc, Tc, false, true>(Einv[2], vz, t1, t0, lam[2], lam[0], lam[1], st);
+    run_axis<Tc, Tc, Tc, false, false>(E[2], vz, t0, t1, nullptr, nullptr, nullptr, st);
+    run_axis<Tc, Tc, Tc, false, false>(E[1], vy, t1, t0, nullptr, nullptr, nullptr, st);
+    run_axis<Tc, Tc, double, true, false>(E[0], vx, t0, phi, nullptr, nullptr, nullptr, st);
+    timing_end(ctx, FVK_STAGE_TRANSFORM, 6);
 }
 
 }  // namespace
