@@ -85,8 +85,9 @@ fvk_status fvk_set_simple(fvk_ctx *ctx, double tol, int max_passes);
  * (nx+2)(ny+2)(nz+2), n_total = 4 * field_len. */
 fvk_status fvk_layout(const fvk_ctx *ctx, size_t off[4], size_t *field_len, size_t *n_total);
 /* Host copies of one axis (0 = x, 1 = y, 2 = z): faces[0..n], centres[0..n+1]
- * (wall nodes included), widths[0..n+1] (widths[i] = f[i] - f[i-1], ends 0).
- * Any pointer may be NULL. */
+ * (wall nodes included), widths[0..n+1] (widths[i] = f[i] - f[i-1] for the
+ * first half, mirrored exactly onto the second since every grid kind is
+ * symmetric about 1/2; ends 0).  Any pointer may be NULL. */
 fvk_status fvk_grid_axis(const fvk_ctx *ctx, int axis, double *faces, double *centres,
                          double *widths);
 const char *fvk_last_error(const fvk_ctx *ctx);

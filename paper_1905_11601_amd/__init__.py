@@ -109,11 +109,11 @@ class Ctx:
         n = self.n[a]
         f = np.zeros(n + 1)
         c = np.zeros(n + 2)
-        w = np.zeros(n + 2)
+        h = np.zeros(n + 2)
         dp = ctypes.POINTER(ctypes.c_double)
         self._check(self.lib.fvk_grid_axis(self.h, a, f.ctypes.data_as(dp), c.ctypes.data_as(dp),
-                                           w.ctypes.data_as(dp)))
-        return f, c, w
+                                           h.ctypes.data_as(dp)))
+        return f, c, h
 
     def coords(self):
         ax = [self.axis(a) for a in range(3)]

@@ -58,6 +58,12 @@ void free_ws(fvk_ctx *ctx) {
         fr(w.E32[a]);
         fr(w.Einv32[a]);
         fr(w.lam32[a]);
+        fr(w.Ah[a]);
+        fr(w.Bh[a]);
+        fr(w.lamp[a]);
+        fr(w.Ah32[a]);
+        fr(w.Bh32[a]);
+        fr(w.lamp32[a]);
     }
     fr(w.vtmp);
     fr(w.vtmp2);
@@ -260,6 +266,7 @@ fvk_status fvk_create(fvk_ctx **out, int nx, int ny, int nz, int grid_kind, doub
     for (int a = 0; a < 3; ++a) {
         build_axis(ctx->ax[a], ctx->n[a], grid_kind, s);
         neumann_eig(ctx->ax[a], ctx->eig[a]);
+        if (ctx->n[a] <= kSymMax) neumann_eig_sym(ctx->ax[a], ctx->esym[a]);
     }
     Geo &g = ctx->geo;
     for (int a = 0; a < 3; ++a) {
@@ -335,6 +342,28 @@ fvk_status fvk_create(fvk_ctx **out, int nx, int ny, int nz, int grid_kind, doub
             hipMemcpy(w.lam32[a], l32.data(), l32.size() * 4, hipMemcpyHostToDevice) !=
                 hipSuccess) {
             st = fail(ctx, FVK_EHIP, "eigenbasis upload failed");
+            goto bad;
+        }
+    }
+    for (int a = 0; a < 3; ++a) {
+        if (ctx->n[a] > kSymMax) continue;
+        const EigSym &e = ctx->esym[a];
+        const size_t ms = e.A.size();
+        std::vector<float> A32(e.A.begin(), e.A.end()), B32(e.B.begin(), e.B.end()),
+            l32(e.lam.begin(), e.lam.end());
+        if ((st = dalloc(ctx, &w.Ah[a], ms)) != FVK_OK) goto bad;
+        if ((st = dalloc(ctx, &w.Bh[a], ms)) != FVK_OK) goto bad;
+        if ((st = dalloc(ctx, &w.lamp[a], e.n)) != FVK_OK) goto bad;
+        if ((st = dalloc(ctx, &w.Ah32[a], ms)) != FVK_OK) goto bad;
+        if ((st = dalloc(ctx, &w.Bh32[a], ms)) != FVK_OK) goto bad;
+        if ((st = dalloc(ctx, &w.lamp32[a], e.n)) != FVK_OK) goto bad;
+        if (hipMemcpy(w.Ah[a], e.A.data(), ms * 8, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(w.Bh[a], e.B.data(), ms * 8, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(w.lamp[a], e.lam.data(), e.n * 8, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(w.Ah32[a], A32.data(), ms * 4, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(w.Bh32[a], B32.data(), ms * 4, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(w.lamp32[a], l32.data(), e.n * 4, hipMemcpyHostToDevice) != hipSuccess) {
+            st = fail(ctx, FVK_EHIP, "half-size eigenbasis upload failed");
             goto bad;
         }
     }

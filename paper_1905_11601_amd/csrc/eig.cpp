@@ -38,6 +38,12 @@ void build_axis(AxisHost &a, int n, int kind, double s) {
     a.c[n + 1] = 1.0;
     for (int i = 1; i <= n; ++i) a.h[i] = a.f[i] - a.f[i - 1];
     for (int i = 0; i <= n; ++i) a.d[i] = a.c[i + 1] - a.c[i];
+    // every grid kind is mirror-symmetric about 1/2; make the widths and
+    // spacings exactly so (the subtractions above differ in the last bits
+    // between mirrored pairs), so that the pressure operator D G is exactly
+    // persymmetric and its eigenvectors split exactly into even and odd ones
+    for (int i = 1; 2 * i <= n + 1; ++i) a.h[n + 1 - i] = a.h[i];
+    for (int i = 0; 2 * i <= n; ++i) a.d[n - i] = a.d[i];
     for (int i = 0; i <= n; ++i) a.w[i] = (a.f[i] - a.c[i]) / a.d[i];
     a.w[0] = 0.0;
     a.w[n] = 1.0;
@@ -162,6 +168,108 @@ void neumann_eig(const AxisHost &a, Eig1D &e) {
         for (int i = 0; i < n; ++i) {
             e.E[size_t(i) * n + q] = col[i] / sh[i];
             e.Einv[size_t(q) * n + i] = col[i] * sh[i];
+        }
+    }
+}
+
+// Even/odd split of the same eigenbasis (exact for the mirror-symmetric
+// axes): with N = 2m or 2m+1 cells, the eigenvectors of the persymmetric S
+// are even or odd about the middle, and the two families are the
+// eigenvectors of two tridiagonal matrices of order ne = N - m and no = m
+// acting on the reduced coordinates c_i = sqrt(2) v_i (i < m; c_m = v_m for
+// odd N).  An axis transform then becomes two half-size products:
+//   forward  E^-1 x:  even coefficients = Ae (x_i + x_{N-1-i}),
+//                     odd coefficients  = Ao (x_i - x_{N-1-i})
+//                     (x_m itself in the last even column for odd N);
+//   inverse  E y:     x_i = (Be y_e)_i + (Bo y_o)_i,
+//                     x_{N-1-i} = (Be y_e)_i - (Bo y_o)_i, x_m = (Be y_e)_m.
+// Coefficients are stored even modes first (each family descending in
+// eigenvalue), so lam is permuted the same way; index 0 is the constant mode.
+void neumann_eig_sym(const AxisHost &a, EigSym &e) {
+    const int n = a.n, m = n / 2, ne = n - m, no = m;
+    std::vector<double> diag(n), off(std::max(n - 1, 1), 0.0);
+    for (int i = 1; i <= n; ++i) {
+        double dg = 0.0;
+        if (i < n) dg -= 1.0 / (a.d[i] * a.h[i]);
+        if (i > 1) dg -= 1.0 / (a.d[i - 1] * a.h[i]);
+        diag[i - 1] = dg;
+        if (i < n) off[i - 1] = 1.0 / (a.d[i] * std::sqrt(a.h[i] * a.h[i + 1]));
+    }
+    // reduced tridiagonal matrices
+    std::vector<double> de(ne), oe(std::max(ne - 1, 1), 0.0), dod(std::max(no, 1)),
+        oo(std::max(no - 1, 1), 0.0);
+    for (int i = 0; i < m; ++i) {
+        de[i] = diag[i];
+        dod[i] = diag[i];
+    }
+    for (int i = 0; i + 1 < m; ++i) {
+        oe[i] = off[i];
+        oo[i] = off[i];
+    }
+    if (n % 2 == 0) {
+        de[m - 1] += off[m - 1];
+        dod[m - 1] -= off[m - 1];
+    } else {
+        de[m] = diag[m];
+        if (m > 0) oe[m - 1] = std::sqrt(2.0) * off[m - 1];
+    }
+    std::vector<double> sh(n);
+    double len = 0.0;
+    for (int i = 0; i < n; ++i) {
+        sh[i] = std::sqrt(a.h[i + 1]);
+        len += a.h[i + 1];
+    }
+    e.n = n;
+    e.ne = ne;
+    e.no = no;
+    e.lam.assign(n, 0.0);
+    e.A.assign(size_t(ne) * ne + size_t(no) * no, 0.0);
+    e.B.assign(e.A.size(), 0.0);
+    // reduced-coordinate weight: sqrt(2) off the middle, 1 at the middle
+    auto red = [&](int i) { return (n % 2 == 1 && i == m) ? 1.0 : std::sqrt(2.0); };
+    for (int fam = 0; fam < 2; ++fam) {
+        const int k = fam == 0 ? ne : no;
+        if (k == 0) continue;
+        std::vector<double> lam(k), Q(size_t(k) * k);
+        tridiag_eig(k, fam == 0 ? de.data() : dod.data(), fam == 0 ? oe.data() : oo.data(),
+                    lam.data(), Q.data());
+        std::vector<int> order(k);
+        std::iota(order.begin(), order.end(), 0);
+        std::sort(order.begin(), order.end(), [&](int p, int q) { return lam[p] > lam[q]; });
+        std::vector<double> c0(k), col(k);
+        if (fam == 0) {   // closed-form null vector in reduced coordinates
+            const double rl = 1.0 / std::sqrt(len);
+            for (int i = 0; i < k; ++i) c0[i] = red(i) * sh[i] * rl;
+        }
+        double *Mf = e.A.data() + (fam == 0 ? 0 : size_t(ne) * ne);
+        double *Mi = e.B.data() + (fam == 0 ? 0 : size_t(ne) * ne);
+        for (int q = 0; q < k; ++q) {
+            const int src = order[q];
+            e.lam[(fam == 0 ? 0 : ne) + q] = (fam == 0 && q == 0) ? 0.0 : lam[src];
+            if (fam == 0 && q == 0) {
+                col = c0;
+            } else {
+                for (int i = 0; i < k; ++i) col[i] = Q[size_t(i) * k + src];
+                double nrm = 0.0;
+                if (fam == 0) {
+                    double dot = 0.0;
+                    for (int i = 0; i < k; ++i) dot += c0[i] * col[i];
+                    for (int i = 0; i < k; ++i) col[i] -= dot * c0[i];
+                }
+                for (int i = 0; i < k; ++i) nrm += col[i] * col[i];
+                double big = 0.0;
+                for (int i = 0; i < k; ++i)
+                    if (std::fabs(col[i]) > std::fabs(big)) big = col[i];
+                const double sc = (big < 0 ? -1.0 : 1.0) / std::sqrt(nrm);
+                for (int i = 0; i < k; ++i) col[i] *= sc;
+            }
+            // full eigenvector entries v_i = col_i / red(i); E^-1 rows carry
+            // sqrt(h), E columns 1 / sqrt(h)
+            for (int i = 0; i < k; ++i) {
+                const double v = col[i] / red(i);
+                Mf[size_t(q) * k + i] = v * sh[i];
+                Mi[size_t(i) * k + q] = v / sh[i];
+            }
         }
     }
 }

@@ -48,6 +48,17 @@ struct Eig1D {
     std::vector<double> lam, E, Einv;
 };
 
+// Axes up to this many cells use the even/odd half-size transforms.
+constexpr int kSymMax = 512;
+
+// Even/odd half-size factors of the same eigenbasis (neumann_eig_sym):
+// A = [Ae (ne x ne) | Ao (no x no)] forward, B = [Be | Bo] inverse, both
+// row-major; lam permuted even modes first.
+struct EigSym {
+    int n = 0, ne = 0, no = 0;
+    std::vector<double> lam, A, B;
+};
+
 // HIP-event stage timing (see fvk_set_timing).
 struct Timing {
     int mask = 0;
@@ -66,6 +77,9 @@ struct Workspace {
     void *tb0 = nullptr, *tb1 = nullptr;   // transform ping-pong buffers (FP64 sized)
     double *E[3] = {}, *Einv[3] = {}, *lam[3] = {};
     float *E32[3] = {}, *Einv32[3] = {}, *lam32[3] = {};
+    // even/odd half-size factors (axes with at most kSymMax cells)
+    double *Ah[3] = {}, *Bh[3] = {}, *lamp[3] = {};
+    float *Ah32[3] = {}, *Bh32[3] = {}, *lamp32[3] = {};
     double *vtmp = nullptr;         // 4-field scratch vector
     double *vtmp2 = nullptr;        // 4-field scratch vector (transposed SIMPLE)
     double *coef_dev = nullptr;     // small coefficient arrays copied from the host
@@ -95,6 +109,7 @@ struct fvk_ctx {
     int mixed_passes = 2;           // fixed pass count of asynchronous mixed calls
     fvk::AxisHost ax[3];
     fvk::Eig1D eig[3];
+    fvk::EigSym esym[3];
     fvk::Geo geo{};
     fvk::Workspace ws;
     fvk::Timing tm;
@@ -111,6 +126,7 @@ void timing_end(fvk_ctx *ctx, int stage, int launches = 1);
 // ---- host utilities (eig.cpp)
 void build_axis(AxisHost &a, int n, int kind, double s);
 void neumann_eig(const AxisHost &a, Eig1D &e);
+void neumann_eig_sym(const AxisHost &a, EigSym &e);
 int tridiag_eig(int n, const double *diag, const double *off, double *lam, double *Q);
 
 // ---- stencil kernels (kernels_stencil.hip); all enqueue on `st`

@@ -134,344 +134,427 @@ __global__ __launch_bounds__(NT) void k_axis(const Tc *__restrict__ M, AxisView 
     }
 }
 
-// Strip kernel: a block owns TN = 16 CT columns and ALL na output rows.  Its
-// input strip (na x TN) is staged in LDS once (k-major, zero-padded to a
-// multiple of 4 in K); the transform matrix M (at most 256 x 256, L2-resident
-// and shared by every block) is streamed from global memory as MFMA
-// A-fragments, so the K loop has no barriers.  Wave w owns the 16-row tiles
-// w, w+4, w+8, ...  For the unit-stride axis the results are transposed
-// through LDS so the stores are coalesced.
-template <typename Tc, typename Tin, typename Tout, bool CONTIG, bool SCALE, int CT, int MAXRT>
-__global__ __launch_bounds__(NT) void k_axis_strip(const Tc *__restrict__ M, AxisView v,
-                                                   const Tin *__restrict__ X,
-                                                   Tout *__restrict__ Y,
-                                                   const Tc *__restrict__ lamR,
-                                                   const Tc *__restrict__ lam0,
-                                                   const Tc *__restrict__ lam1) {
-    constexpr int TN = 16 * CT;
-    constexpr int LDX = TN + 1;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    Tc *sX = reinterpret_cast<Tc *>(smem_raw);
-    typedef typename Mfma<Tc>::acc acc_t;
-    const int na = v.na;
-    const int Kp = (na + 3) & ~3;
-    const int col0 = blockIdx.x * TN;
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int e = tid; e < Kp * TN; e += NT) {
-        int k, cc;
-        if (CONTIG) {
-            k = e % Kp;
-            cc = e / Kp;
-        } else {
-            cc = e % TN;
-            k = e / TN;
-        }
-        const int gc = col0 + cc;
-        const bool ok = k < na && gc < v.ncols;
-        const Tin val = X[col_addr(v, min(gc, v.ncols - 1)) + long(min(k, na - 1)) * v.sb];
-        sX[k * LDX + cc] = ok ? Tc(val) : Tc(0);
-    }
-    __syncthreads();
-    const int RT = (na + 15) >> 4;
-    acc_t acc[MAXRT][CT];
-#pragma unroll
-    for (int q = 0; q < MAXRT; ++q)
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) acc[q][ct] = acc_t{0, 0, 0, 0};
-    const int lr = lane & 15, lk = lane >> 4;
-    // A-fragments stream from global memory through an AD-deep register ring
-    // so AD loads per row tile are in flight while the MFMAs consume older ones
-    constexpr int AD = 8;
-    auto loadA = [&](int q, int k4) -> Tc {
-        const int row = (wv + 4 * q) * 16 + lr;
-        const int kk = k4 + lk;
-        const Tc a0 = M[long(min(row, na - 1)) * na + min(kk, na - 1)];
-        return (row < na && kk < na) ? a0 : Tc(0);
-    };
-    Tc ar[MAXRT][AD];
-#pragma unroll
-    for (int d = 0; d < AD; ++d)
-#pragma unroll
-        for (int q = 0; q < MAXRT; ++q) ar[q][d] = loadA(q, 4 * d);
-    for (int kb4 = 0; kb4 < Kp; kb4 += 4 * AD) {
-#pragma unroll
-        for (int d = 0; d < AD; ++d) {
-            const int k4 = kb4 + 4 * d;
-            if (k4 < Kp) {
-                const int kk = k4 + lk;
-                Tc bfr[CT];
-#pragma unroll
-                for (int ct = 0; ct < CT; ++ct) bfr[ct] = sX[kk * LDX + ct * 16 + lr];
-#pragma unroll
-                for (int q = 0; q < MAXRT; ++q) {
-                    if (wv + 4 * q < RT) {
-#pragma unroll
-                        for (int ct = 0; ct < CT; ++ct)
-                            acc[q][ct] = Mfma<Tc>::op(ar[q][d], bfr[ct], acc[q][ct]);
-                    }
-                    ar[q][d] = loadA(q, k4 + 4 * AD);
-                }
-            }
-        }
-    }
-    auto scaled = [&](Tc val, int row, int col) -> Tc {
-        if (SCALE) {
-            const Tc l = lamR[row] + lam0[col % v.n0] + lam1[col / v.n0];
-            return (row == 0 && col == 0) ? Tc(0) : val / l;
-        }
-        return val;
-    };
-    if (!CONTIG) {
-#pragma unroll
-        for (int q = 0; q < MAXRT; ++q) {
-            const int rt = wv + 4 * q;
-            if (rt >= RT) continue;
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct) {
-                const int col = col0 + ct * 16 + lr;
-                if (col >= v.ncols) continue;
-                const long ca = col_addr(v, col);
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = rt * 16 + Mfma<Tc>::row(lane, r);
-                    if (row < na) Y[ca + long(row) * v.sb] = Tout(scaled(acc[q][ct][r], row, col));
-                }
-            }
-        }
-        return;
-    }
-    // unit-stride axis: transpose through LDS ([col][row], pitch Kp + 1)
-    __syncthreads();
-    const int LDO = Kp + 1;
-#pragma unroll
-    for (int q = 0; q < MAXRT; ++q) {
-        const int rt = wv + 4 * q;
-        if (rt >= RT) continue;
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = rt * 16 + Mfma<Tc>::row(lane, r);
-                if (row < Kp) sX[(ct * 16 + lr) * LDO + row] = acc[q][ct][r];
-            }
-    }
-    __syncthreads();
-    for (int e = tid; e < TN * na; e += NT) {
-        const int cc = e / na, row = e % na;
-        const int col = col0 + cc;
-        if (col < v.ncols)
-            Y[col_addr(v, col) + row] = Tout(scaled(sX[cc * LDO + row], row, col));
-    }
-}
-
-template <typename Tc, typename Tin, typename Tout, bool CONTIG, bool SCALE, int CT, int MAXRT>
-void launch_strip(const Tc *M, const AxisView &v, const Tin *X, Tout *Y, const Tc *lR,
-                  const Tc *l0, const Tc *l1, hipStream_t st) {
-    const int Kp = (v.na + 3) & ~3;
-    const size_t lds = std::max(size_t(Kp) * (16 * CT + 1), size_t(16 * CT) * (Kp + 1)) * sizeof(Tc);
-    const int nb = (v.ncols + 16 * CT - 1) / (16 * CT);
-    k_axis_strip<Tc, Tin, Tout, CONTIG, SCALE, CT, MAXRT><<<nb, NT, lds, st>>>(M, v, X, Y, lR, l0, l1);
-}
-
-template <typename Tc, typename Tin, typename Tout, bool CONTIG, bool SCALE, int CT>
-bool strip_dispatch(const Tc *M, const AxisView &v, const Tin *X, Tout *Y, const Tc *lR,
-                    const Tc *l0, const Tc *l1, hipStream_t st) {
-    const int rt = (v.na + 15) / 16;
-    const int maxrt = (rt + 3) / 4;
-    switch (maxrt) {
-        case 1: launch_strip<Tc, Tin, Tout, CONTIG, SCALE, CT, 1>(M, v, X, Y, lR, l0, l1, st); return true;
-        case 2: launch_strip<Tc, Tin, Tout, CONTIG, SCALE, CT, 2>(M, v, X, Y, lR, l0, l1, st); return true;
-        case 3: launch_strip<Tc, Tin, Tout, CONTIG, SCALE, CT, 3>(M, v, X, Y, lR, l0, l1, st); return true;
-        case 4: launch_strip<Tc, Tin, Tout, CONTIG, SCALE, CT, 4>(M, v, X, Y, lR, l0, l1, st); return true;
-        default: return false;
-    }
-}
-
-// GEMM-style transform: Y(P, T) = sum_K M[T][K] X(P, K) for every pencil P of
-// the block's tile of 16 CP pencils and ALL transform outputs T (padded to
-// 16 MAXRT per wave x 4 waves), so each input value is read from HBM once.
-// Both operands stream through LDS in K-chunks of KC, double-buffered: the
-// next chunk's global loads are in flight (in registers) while the MFMAs
-// consume the current one; one barrier per chunk.  LDS tiles are K-major:
-// sM[k][t], sX[k][p].  For the y/z axes the MFMA rows are T (A = M) and the
-// 16 lanes of a result row are 16 consecutive pencils; for the unit-stride x
-// axis (XAX) the roles swap (A = X, B = M^T) so the 16 lanes hold 16
-// consecutive T -- contiguous -- and all stores are coalesced.
-template <int MAXRT, int CP>
-struct GemmTile {
+// Even/odd transform of a mirror-symmetric axis (the half-size factors of
+// neumann_eig_sym).  A block computes all outputs of a tile of 16 CP pencils
+// with NW wavefronts; wave w owns output rows [16 w, 16 w + 16) of BOTH
+// halves, so NW = ceil(ne / 16) leaves at most 15 padded rows.  Both
+// operands stream through LDS in K-chunks of KC, double-buffered (the next
+// chunk's global loads are in flight in registers while the MFMAs consume the
+// current one; one barrier per chunk).  Two products of half the order run
+// side by side:
+//   FWD: even = Ae (x_k + x_{N-1-k}), odd = Ao (x_k - x_{N-1-k}) (the middle
+//        value x_m enters the last even column when N is odd); outputs are
+//        stored even modes first, SCALE multiplies by the reciprocal of the
+//        (permuted) eigenvalue sums;
+//   INV: P = Be y_even, Q = Bo y_odd; x_t = P_t + Q_t, x_{N-1-t} = P_t - Q_t
+//        (x_m = P_m for odd N); P and Q of a row sit in the same lane.
+// Half the flops and half the matrix entries of the full transform.  For the
+// unit-stride x axis (XAX) the MFMA roles swap (A = X, B = M^T) so that the
+// 16 lanes of a result row hold 16 consecutive transform indices and the
+// stores are coalesced.
+template <int NW, int CP>
+struct SymTile {
     static constexpr int KC = 16;
-    static constexpr int TT = 64 * MAXRT;          // T rows held (4 waves x MAXRT tiles)
+    static constexpr int NTT = 64 * NW;            // threads
+    static constexpr int TT = 16 * NW;             // rows per half
     static constexpr int TP = 16 * CP;             // pencils per block
     static constexpr int LDT = TT + 1, LDP = TP + 1;
-    static constexpr int NM = (TT * KC + NT - 1) / NT;   // M chunk entries per thread
-    static constexpr int NX = (TP * KC + NT - 1) / NT;   // X chunk entries per thread
+    static constexpr int NM = (TT * KC + NTT - 1) / NTT;
+    static constexpr int NX = (TP * KC + NTT - 1) / NTT;
 };
 
-template <typename Tc, typename Tin, typename Tout, bool XAX, bool SCALE, int MAXRT, int CP>
-__global__ __launch_bounds__(NT) void k_axis_gemm(const Tc *__restrict__ M, AxisView v,
-                                                  const Tin *__restrict__ X,
-                                                  Tout *__restrict__ Y,
-                                                  const Tc *__restrict__ lamR,
-                                                  const Tc *__restrict__ lam0,
-                                                  const Tc *__restrict__ lam1) {
-    typedef GemmTile<MAXRT, CP> G;
-    constexpr int KC = G::KC, TT = G::TT, TP = G::TP, LDT = G::LDT, LDP = G::LDP;
-    __shared__ Tc sM[2][KC * LDT];
-    __shared__ Tc sX[2][KC * LDP];
+// 1 / d to full double precision: hardware estimate + two Newton steps
+__device__ __forceinline__ double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+    r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
+    return r;
+}
+__device__ __forceinline__ float recip(float d) { return 1.0f / d; }
+
+template <typename Tc, typename Tin, typename Tout, bool XAX, bool SCALE, bool FWD, int NW,
+          int CP>
+__global__ __launch_bounds__(64 * NW) void k_axis_sym(const Tc *__restrict__ M, AxisView v,
+                                                      const Tin *__restrict__ X,
+                                                      Tout *__restrict__ Y,
+                                                      const Tc *__restrict__ lamR,
+                                                      const Tc *__restrict__ lam0,
+                                                      const Tc *__restrict__ lam1) {
+    typedef SymTile<NW, CP> G;
+    constexpr int KC = G::KC, TT = G::TT, TP = G::TP, LDT = G::LDT, LDP = G::LDP,
+                  NTT = G::NTT;
+    __shared__ Tc sM[2][2][KC * LDT];   // [buffer][even/odd]
+    __shared__ Tc sX[2][2][KC * LDP];
     typedef typename Mfma<Tc>::acc acc_t;
-    const int na = v.na;
+    const int n = v.na, nh = n / 2, ne = n - nh, no = nh;
+    const Tc *Me = M, *Mo = M + long(ne) * ne;
     const int p0 = blockIdx.x * TP;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int nchunk = (na + KC - 1) / KC;
-    Tc rm[G::NM], rx[G::NX];
-    // global -> registers for chunk c (zero outside the matrix / pencil range)
+    const int nchunk = (ne + KC - 1) / KC;
+    // fetch only issues loads (raw values, clamped addresses); masking and the
+    // even/odd fold happen in put, after the MFMAs of the current chunk
+    Tc rme[G::NM], rmo[G::NM], rxa[G::NX], rxb[G::NX];
     auto fetch = [&](int c) {
         const int kb = c * KC;
 #pragma unroll
         for (int q = 0; q < G::NM; ++q) {
-            const int e = tid + q * NT;
-            const int t = e / KC, kk = e % KC;
-            const bool ok = e < TT * KC && t < na && kb + kk < na;
-            const Tc val = M[long(min(t, na - 1)) * na + min(kb + kk, na - 1)];
-            rm[q] = ok ? val : Tc(0);
+            const int e = tid + q * NTT;
+            const int t = e / KC, k = kb + e % KC;
+            rme[q] = Me[long(min(t, ne - 1)) * ne + min(k, ne - 1)];
+            rmo[q] = Mo[long(min(t, no - 1)) * no + min(k, no - 1)];
         }
 #pragma unroll
         for (int q = 0; q < G::NX; ++q) {
-            const int e = tid + q * NT;
-            int p, kk;
-            if (XAX) {
-                p = e / KC;
-                kk = e % KC;
+            const int e = tid + q * NTT;
+            const int p = XAX ? e / KC : e % TP, kk = XAX ? e % KC : e / TP;
+            const int k = kb + kk;
+            const long base = col_addr(v, min(p0 + p, v.ncols - 1));
+            if (FWD) {
+                const int kc = min(k, n - 1);
+                rxa[q] = Tc(X[base + long(kc) * v.sb]);
+                rxb[q] = Tc(X[base + long(n - 1 - kc) * v.sb]);
             } else {
-                kk = e / TP;
-                p = e % TP;
+                rxa[q] = Tc(X[base + long(min(k, ne - 1)) * v.sb]);
+                rxb[q] = Tc(X[base + long(ne + min(k, no - 1)) * v.sb]);
             }
-            const int gp = p0 + p, k = kb + kk;
-            const bool ok = e < TP * KC && gp < v.ncols && k < na;
-            const Tin val = X[col_addr(v, min(gp, v.ncols - 1)) + long(min(k, na - 1)) * v.sb];
-            rx[q] = ok ? Tc(val) : Tc(0);
         }
     };
-    auto put = [&](int buf) {
+    auto put = [&](int buf, int c) {
+        const int kb = c * KC;
 #pragma unroll
         for (int q = 0; q < G::NM; ++q) {
-            const int e = tid + q * NT;
-            if (e < TT * KC) sM[buf][(e % KC) * LDT + e / KC] = rm[q];
+            const int e = tid + q * NTT;
+            const int t = e / KC, k = kb + e % KC;
+            if (e < TT * KC) {
+                sM[buf][0][(e % KC) * LDT + t] = (t < ne && k < ne) ? rme[q] : Tc(0);
+                sM[buf][1][(e % KC) * LDT + t] = (t < no && k < no) ? rmo[q] : Tc(0);
+            }
         }
 #pragma unroll
         for (int q = 0; q < G::NX; ++q) {
-            const int e = tid + q * NT;
+            const int e = tid + q * NTT;
+            const int p = XAX ? e / KC : e % TP, kk = XAX ? e % KC : e / TP;
+            const int k = kb + kk;
             if (e < TP * KC) {
-                if (XAX)
-                    sX[buf][(e % KC) * LDP + e / KC] = rx[q];
-                else
-                    sX[buf][(e / TP) * LDP + e % TP] = rx[q];
+                const bool in = p0 + p < v.ncols;
+                Tc a, b;
+                if (FWD) {
+                    a = k < no ? rxa[q] + rxb[q] : (k < ne ? rxa[q] : Tc(0));   // middle
+                    b = k < no ? rxa[q] - rxb[q] : Tc(0);
+                } else {
+                    a = k < ne ? rxa[q] : Tc(0);
+                    b = k < no ? rxb[q] : Tc(0);
+                }
+                sX[buf][0][kk * LDP + p] = in ? a : Tc(0);
+                sX[buf][1][kk * LDP + p] = in ? b : Tc(0);
             }
         }
     };
-    acc_t acc[MAXRT][CP];
+    acc_t ae[CP], ao[CP];
 #pragma unroll
-    for (int q = 0; q < MAXRT; ++q)
-#pragma unroll
-        for (int cp = 0; cp < CP; ++cp) acc[q][cp] = acc_t{0, 0, 0, 0};
+    for (int cp = 0; cp < CP; ++cp) {
+        ae[cp] = acc_t{0, 0, 0, 0};
+        ao[cp] = acc_t{0, 0, 0, 0};
+    }
     fetch(0);
-    put(0);
+    put(0, 0);
     lds_barrier();
+    const int tb = wv * 16;
     for (int c = 0; c < nchunk; ++c) {
         const int buf = c & 1;
         if (c + 1 < nchunk) fetch(c + 1);
 #pragma unroll
         for (int k4 = 0; k4 < KC; k4 += 4) {
             const int kk = k4 + lk;
-            Tc mf[MAXRT], xf[CP];
+            const Tc me = sM[buf][0][kk * LDT + tb + lr];
+            const Tc mo = sM[buf][1][kk * LDT + tb + lr];
 #pragma unroll
-            for (int q = 0; q < MAXRT; ++q) mf[q] = sM[buf][kk * LDT + (wv + 4 * q) * 16 + lr];
-#pragma unroll
-            for (int cp = 0; cp < CP; ++cp) xf[cp] = sX[buf][kk * LDP + cp * 16 + lr];
-#pragma unroll
-            for (int q = 0; q < MAXRT; ++q)
-#pragma unroll
-                for (int cp = 0; cp < CP; ++cp)
-                    acc[q][cp] = XAX ? Mfma<Tc>::op(xf[cp], mf[q], acc[q][cp])
-                                     : Mfma<Tc>::op(mf[q], xf[cp], acc[q][cp]);
+            for (int cp = 0; cp < CP; ++cp) {
+                const Tc xe = sX[buf][0][kk * LDP + cp * 16 + lr];
+                const Tc xo = sX[buf][1][kk * LDP + cp * 16 + lr];
+                ae[cp] = XAX ? Mfma<Tc>::op(xe, me, ae[cp]) : Mfma<Tc>::op(me, xe, ae[cp]);
+                ao[cp] = XAX ? Mfma<Tc>::op(xo, mo, ao[cp]) : Mfma<Tc>::op(mo, xo, ao[cp]);
+            }
         }
-        if (c + 1 < nchunk) put(buf ^ 1);
+        if (c + 1 < nchunk) put(buf ^ 1, c + 1);
         lds_barrier();
     }
+    if (tb >= ne) return;
 #pragma unroll
-    for (int q = 0; q < MAXRT; ++q) {
-        const int tb = (wv + 4 * q) * 16;
-        if (tb >= na) continue;
+    for (int cp = 0; cp < CP; ++cp)
 #pragma unroll
-        for (int cp = 0; cp < CP; ++cp)
+        for (int r = 0; r < 4; ++r) {
+            int t, pp;
+            if (XAX) {
+                t = tb + lr;
+                pp = p0 + cp * 16 + Mfma<Tc>::row(lane, r);
+            } else {
+                t = tb + Mfma<Tc>::row(lane, r);
+                pp = p0 + cp * 16 + lr;
+            }
+            if (t >= ne || pp >= v.ncols) continue;
+            const long base = col_addr(v, pp);
+            const Tc pe = ae[cp][r], po = ao[cp][r];
+            if (FWD) {
+                Tc ve = pe, vo = po;
+                if (SCALE) {
+                    const Tc l01 = lam0[pp % v.n0] + lam1[pp / v.n0];
+                    ve = (t == 0 && pp == 0) ? Tc(0) : pe * recip(lamR[t] + l01);
+                    if (t < no) vo = po * recip(lamR[ne + t] + l01);
+                }
+                Y[base + long(t) * v.sb] = Tout(ve);
+                if (t < no) Y[base + long(ne + t) * v.sb] = Tout(vo);
+            } else {
+                if (t < no) {
+                    Y[base + long(t) * v.sb] = Tout(pe + po);
+                    Y[base + long(n - 1 - t) * v.sb] = Tout(pe - po);
+                } else {
+                    Y[base + long(t) * v.sb] = Tout(pe);   // the middle (odd N)
+                }
+            }
+        }
+}
+
+template <typename Tc, typename Tin, typename Tout, bool XAX, bool SCALE, bool FWD, int NW, int CP>
+void launch_sym(const Tc *M, const AxisView &v, const Tin *X, Tout *Y, const Tc *lR,
+                const Tc *l0, const Tc *l1, hipStream_t st) {
+    const int nb = (v.ncols + 16 * CP - 1) / (16 * CP);
+    k_axis_sym<Tc, Tin, Tout, XAX, SCALE, FWD, NW, CP>
+        <<<nb, 64 * NW, 0, st>>>(M, v, X, Y, lR, l0, l1);
+}
+
+// one wave per 16 rows of the half length ne = ceil(N/2) <= 256; two pencil
+// tiles per block when that still leaves >= 1024 blocks
+template <typename Tc, typename Tin, typename Tout, bool XAX, bool SCALE, bool FWD>
+void run_sym(const Tc *M, const AxisView &v, const Tin *X, Tout *Y, const Tc *lR, const Tc *l0,
+             const Tc *l1, hipStream_t st) {
+    const int ne = v.na - v.na / 2;
+    const int nw = (ne + 15) / 16;
+    const bool cp2 = (v.ncols + 31) / 32 >= 1024;
+#define FVK_SYM_CASE(W)                                                                    \
+    case W:                                                                                \
+        if (cp2)                                                                           \
+            launch_sym<Tc, Tin, Tout, XAX, SCALE, FWD, W, 2>(M, v, X, Y, lR, l0, l1, st);  \
+        else                                                                               \
+            launch_sym<Tc, Tin, Tout, XAX, SCALE, FWD, W, 1>(M, v, X, Y, lR, l0, l1, st);  \
+        return;
+    switch (nw) {
+        FVK_SYM_CASE(1)
+        FVK_SYM_CASE(2)
+        FVK_SYM_CASE(3)
+        FVK_SYM_CASE(4)
+        FVK_SYM_CASE(5)
+        FVK_SYM_CASE(6)
+        FVK_SYM_CASE(7)
+        FVK_SYM_CASE(8)
+        default:
+            if (nw <= 12)
+                launch_sym<Tc, Tin, Tout, XAX, SCALE, FWD, 12, 1>(M, v, X, Y, lR, l0, l1, st);
+            else
+                launch_sym<Tc, Tin, Tout, XAX, SCALE, FWD, 16, 1>(M, v, X, Y, lR, l0, l1, st);
+            return;
+    }
+#undef FVK_SYM_CASE
+}
+
+// Register-resident variant of k_axis_sym for ne = ceil(N/2) <= 16 NW: wave w
+// keeps its 16-row slices of Ae/Ao (or Be/Bo) for the whole K range in
+// registers, loaded once, and the block walks over pencil tiles of 16
+// (persistent grid).  Only the pencil data goes through LDS: the whole K
+// extent of the next tile is fetched into registers while the MFMAs consume
+// the current tile, then written to the other LDS buffer -- one barrier per
+// tile.  K and the rows are padded to 16 NW with zeros.
+template <typename Tc, typename Tin, typename Tout, bool XAX, bool SCALE, bool FWD, int NW>
+__global__ __launch_bounds__(64 * NW) void k_axis_res(const Tc *__restrict__ M, AxisView v,
+                                                      const Tin *__restrict__ X,
+                                                      Tout *__restrict__ Y,
+                                                      const Tc *__restrict__ lamR,
+                                                      const Tc *__restrict__ lam0,
+                                                      const Tc *__restrict__ lam1) {
+    constexpr int NTT = 64 * NW, KP = 16 * NW, KS = KP / 4, LDP = 17;
+    constexpr int NXT = KP * 16 / NTT;   // pencil values per thread and half (= 4)
+    __shared__ Tc sX[2][2][KP * LDP];
+    typedef typename Mfma<Tc>::acc acc_t;
+    const int n = v.na, nh = n / 2, ne = n - nh, no = nh;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int tb = wv * 16;
+    const int ntiles = (v.ncols + 15) / 16;
+    // this wave's rows of both factors: lane holds M[tb + lr][4 s + lk]
+    Tc me[KS], mo[KS];
+    {
+        const Tc *Me = M, *Mo = M + long(ne) * ne;
+        const int t = tb + lr;
+#pragma unroll
+        for (int s4 = 0; s4 < KS; ++s4) {
+            const int k = 4 * s4 + lk;
+            const Tc ve = Me[long(min(t, ne - 1)) * ne + min(k, ne - 1)];
+            const Tc vo = Mo[long(min(t, no - 1)) * no + min(k, no - 1)];
+            me[s4] = (t < ne && k < ne) ? ve : Tc(0);
+            mo[s4] = (t < no && k < no) ? vo : Tc(0);
+        }
+    }
+    // fetch only issues the loads (raw values, clamped addresses); the fold
+    // and the masking happen in put, after the MFMAs of the current tile, so
+    // the loads stay in flight meanwhile
+    Tc ra[NXT], rb[NXT];
+    auto pk = [&](int q, int &p, int &k) {
+        const int e = tid + q * NTT;
+        if (XAX) {
+            p = e / KP;
+            k = e % KP;
+        } else {
+            k = e / 16;
+            p = e % 16;
+        }
+    };
+    auto fetch = [&](int tile) {
+#pragma unroll
+        for (int q = 0; q < NXT; ++q) {
+            int p, k;
+            pk(q, p, k);
+            const long base = col_addr(v, min(tile * 16 + p, v.ncols - 1));
+            if (FWD) {
+                const int kc = min(k, n - 1);
+                ra[q] = Tc(X[base + long(kc) * v.sb]);
+                rb[q] = Tc(X[base + long(n - 1 - kc) * v.sb]);
+            } else {
+                ra[q] = Tc(X[base + long(min(k, ne - 1)) * v.sb]);
+                rb[q] = Tc(X[base + long(ne + min(k, no - 1)) * v.sb]);
+            }
+        }
+    };
+    auto put = [&](int buf, int tile) {
+#pragma unroll
+        for (int q = 0; q < NXT; ++q) {
+            int p, k;
+            pk(q, p, k);
+            const bool in = tile * 16 + p < v.ncols;
+            Tc a, b;
+            if (FWD) {
+                a = k < no ? ra[q] + rb[q] : (k < ne ? ra[q] : Tc(0));   // k == m: middle
+                b = k < no ? ra[q] - rb[q] : Tc(0);
+            } else {
+                a = k < ne ? ra[q] : Tc(0);
+                b = k < no ? rb[q] : Tc(0);
+            }
+            const int o = k * LDP + p;
+            sX[buf][0][o] = in ? a : Tc(0);
+            sX[buf][1][o] = in ? b : Tc(0);
+        }
+    };
+    int tile = blockIdx.x;
+    if (tile >= ntiles) return;   // uniform per block
+    fetch(tile);
+    put(0, tile);
+    lds_barrier();
+    int buf = 0;
+    while (true) {
+        const int next = tile + gridDim.x;
+        if (next < ntiles) fetch(next);
+        acc_t ae = {0, 0, 0, 0}, ao = {0, 0, 0, 0};
+#pragma unroll
+        for (int s4 = 0; s4 < KS; ++s4) {
+            const int kk = 4 * s4 + lk;
+            const Tc xe = sX[buf][0][kk * LDP + lr];
+            const Tc xo = sX[buf][1][kk * LDP + lr];
+            ae = XAX ? Mfma<Tc>::op(xe, me[s4], ae) : Mfma<Tc>::op(me[s4], xe, ae);
+            ao = XAX ? Mfma<Tc>::op(xo, mo[s4], ao) : Mfma<Tc>::op(mo[s4], xo, ao);
+        }
+        if (tb < ne) {
+            const int p0 = tile * 16;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 int t, pp;
                 if (XAX) {
                     t = tb + lr;
-                    pp = p0 + cp * 16 + Mfma<Tc>::row(lane, r);
+                    pp = p0 + Mfma<Tc>::row(lane, r);
                 } else {
                     t = tb + Mfma<Tc>::row(lane, r);
-                    pp = p0 + cp * 16 + lr;
+                    pp = p0 + lr;
                 }
-                if (t >= na || pp >= v.ncols) continue;
-                Tc val = acc[q][cp][r];
-                if (SCALE) {
-                    const Tc l = lamR[t] + lam0[pp % v.n0] + lam1[pp / v.n0];
-                    val = (t == 0 && pp == 0) ? Tc(0) : val / l;
+                if (t >= ne || pp >= v.ncols) continue;
+                const long base = col_addr(v, pp);
+                const Tc pe = ae[r], po = ao[r];
+                if (FWD) {
+                    Tc ve = pe, vo = po;
+                    if (SCALE) {
+                        const Tc l01 = lam0[pp % v.n0] + lam1[pp / v.n0];
+                        ve = (t == 0 && pp == 0) ? Tc(0) : pe * recip(lamR[t] + l01);
+                        if (t < no) vo = po * recip(lamR[ne + t] + l01);
+                    }
+                    Y[base + long(t) * v.sb] = Tout(ve);
+                    if (t < no) Y[base + long(ne + t) * v.sb] = Tout(vo);
+                } else {
+                    if (t < no) {
+                        Y[base + long(t) * v.sb] = Tout(pe + po);
+                        Y[base + long(n - 1 - t) * v.sb] = Tout(pe - po);
+                    } else {
+                        Y[base + long(t) * v.sb] = Tout(pe);   // the middle (odd N)
+                    }
                 }
-                Y[col_addr(v, pp) + long(t) * v.sb] = Tout(val);
             }
+        }
+        if (next >= ntiles) break;
+        put(buf ^ 1, next);
+        lds_barrier();
+        buf ^= 1;
+        tile = next;
     }
 }
 
-template <typename Tc, typename Tin, typename Tout, bool XAX, bool SCALE, int MAXRT, int CP>
-void launch_gemm(const Tc *M, const AxisView &v, const Tin *X, Tout *Y, const Tc *lR,
-                 const Tc *l0, const Tc *l1, hipStream_t st) {
-    const int nb = (v.ncols + 16 * CP - 1) / (16 * CP);
-    k_axis_gemm<Tc, Tin, Tout, XAX, SCALE, MAXRT, CP><<<nb, NT, 0, st>>>(M, v, X, Y, lR, l0, l1);
+template <typename Tc, typename Tin, typename Tout, bool XAX, bool SCALE, bool FWD, int NW>
+void launch_res(const Tc *M, const AxisView &v, const Tin *X, Tout *Y, const Tc *lR,
+                const Tc *l0, const Tc *l1, hipStream_t st) {
+    // a few resident blocks per compute unit (256 CUs), each walking tiles
+    const int ntiles = (v.ncols + 15) / 16;
+    const int per_cu = NW <= 4 ? 2 : 1;
+    const int nb = std::min(ntiles, 256 * per_cu);
+    k_axis_res<Tc, Tin, Tout, XAX, SCALE, FWD, NW><<<nb, 64 * NW, 0, st>>>(M, v, X, Y, lR, l0, l1);
 }
 
-// pick the per-wave row tiles from the transform length (<= 256) and the
-// pencils per block so the grid has enough blocks to fill the chip
-template <typename Tc, typename Tin, typename Tout, bool XAX, bool SCALE>
-bool gemm_dispatch(const Tc *M, const AxisView &v, const Tin *X, Tout *Y, const Tc *lR,
-                   const Tc *l0, const Tc *l1, hipStream_t st) {
-    const int maxrt = ((v.na + 15) / 16 + 3) / 4;
-    const bool cp2 = (v.ncols + 31) / 32 >= 1024;
-#define FVK_GEMM_CASE(R)                                                                   \
-    case R:                                                                                \
-        if (cp2)                                                                           \
-            launch_gemm<Tc, Tin, Tout, XAX, SCALE, R, 2>(M, v, X, Y, lR, l0, l1, st);      \
-        else                                                                               \
-            launch_gemm<Tc, Tin, Tout, XAX, SCALE, R, 1>(M, v, X, Y, lR, l0, l1, st);      \
-        return true;
-    switch (maxrt) {
-        FVK_GEMM_CASE(1)
-        FVK_GEMM_CASE(2)
-        FVK_GEMM_CASE(3)
-        FVK_GEMM_CASE(4)
-        default:
-            return false;
-    }
-#undef FVK_GEMM_CASE
+// 96 < ne <= 128 (the MFMA-bound sizes): register-resident factors; shorter
+// axes (latency-bound) and longer ones: the streaming kernel
+template <typename Tc, typename Tin, typename Tout, bool XAX, bool SCALE, bool FWD>
+void run_half(const Tc *M, const AxisView &v, const Tin *X, Tout *Y, const Tc *lR,
+              const Tc *l0, const Tc *l1, hipStream_t st) {
+    const int ne = v.na - v.na / 2;
+    if (ne > 96 && ne <= 128)
+        launch_res<Tc, Tin, Tout, XAX, SCALE, FWD, 8>(M, v, X, Y, lR, l0, l1, st);
+    else
+        run_sym<Tc, Tin, Tout, XAX, SCALE, FWD>(M, v, X, Y, lR, l0, l1, st);
 }
 
+// full-matrix transform (axes longer than kSymMax cells)
 template <typename Tc, typename Tin, typename Tout, bool CONTIG, bool SCALE>
 void run_axis(const Tc *M, const AxisView &v, const Tin *X, Tout *Y, const Tc *lR, const Tc *l0,
               const Tc *l1, hipStream_t st) {
-    // strip kernel for transform lengths up to 256; one or two column tiles
-    // per block depending on how many blocks that gives
-    if (gemm_dispatch<Tc, Tin, Tout, CONTIG, SCALE>(M, v, X, Y, lR, l0, l1, st)) return;
     dim3 grid((v.ncols + TN - 1) / TN, (v.na + TM - 1) / TM);
     k_axis<Tc, Tin, Tout, CONTIG, SCALE><<<grid, NT, 0, st>>>(M, v, X, Y, lR, l0, l1);
 }
 
 
+// Factors of one axis: the even/odd halves when the axis has at most kSymMax
+// cells, else the full matrices; lam in the matching mode order.
 template <typename Tc>
-void tpf_typed(fvk_ctx *ctx, const double *b, double *phi, const Tc *const *E,
-               const Tc *const *Einv, const Tc *const *lam, hipStream_t st) {
+struct AxisFactors {
+    const Tc *fwd, *inv, *lam;
+    bool sym;
+};
+
+template <typename Tc, typename Tin, typename Tout, bool XAX, bool SCALE, bool FWD>
+void axis_step(const AxisFactors<Tc> &f, const AxisView &v, const Tin *X, Tout *Y,
+               const Tc *lR, const Tc *l0, const Tc *l1, hipStream_t st) {
+    if (f.sym)
+        run_half<Tc, Tin, Tout, XAX, SCALE, FWD>(FWD ? f.fwd : f.inv, v, X, Y, lR, l0, l1, st);
+    else
+        run_axis<Tc, Tin, Tout, XAX, SCALE>(FWD ? f.fwd : f.inv, v, X, Y, lR, l0, l1, st);
+}
+
+template <typename Tc>
+void tpf_typed(fvk_ctx *ctx, const double *b, double *phi, const AxisFactors<Tc> *F,
+               hipStream_t st) {
     const int nx = ctx->n[0], ny = ctx->n[1], nz = ctx->n[2];
     const long pl = long(nx) * ny;
     // axis x: rows i, columns (k, j); axis y: rows j, columns (k, i);
@@ -481,30 +564,38 @@ void tpf_typed(fvk_ctx *ctx, const double *b, double *phi, const Tc *const *E,
     const AxisView vz{nz, pl, nx, 1, nx, nx * ny};
     Tc *t0 = static_cast<Tc *>(ctx->ws.tb0);
     Tc *t1 = static_cast<Tc *>(ctx->ws.tb1);
+    const Tc *none = nullptr;
     // one event pair around the six back-to-back launches
     timing_begin(ctx, FVK_STAGE_TRANSFORM);
-    run_axis<Tc, double, Tc, true, false>(Einv[0], vx, b, t0, nullptr, nullptr, nullptr, st);
-    run_axis<Tc, Tc, Tc, false, false>(Einv[1], vy, t0, t1, nullptr, nullptr, nullptr, st);
-    run_axis<Tc, Tc, Tc, false, true>(Einv[2], vz, t1, t0, lam[2], lam[0], lam[1], st);
-    run_axis<Tc, Tc, Tc, false, false>(E[2], vz, t0, t1, nullptr, nullptr, nullptr, st);
-    run_axis<Tc, Tc, Tc, false, false>(E[1], vy, t1, t0, nullptr, nullptr, nullptr, st);
-    run_axis<Tc, Tc, double, true, false>(E[0], vx, t0, phi, nullptr, nullptr, nullptr, st);
+    axis_step<Tc, double, Tc, true, false, true>(F[0], vx, b, t0, none, none, none, st);
+    axis_step<Tc, Tc, Tc, false, false, true>(F[1], vy, t0, t1, none, none, none, st);
+    axis_step<Tc, Tc, Tc, false, true, true>(F[2], vz, t1, t0, F[2].lam, F[0].lam, F[1].lam, st);
+    axis_step<Tc, Tc, Tc, false, false, false>(F[2], vz, t0, t1, none, none, none, st);
+    axis_step<Tc, Tc, Tc, false, false, false>(F[1], vy, t1, t0, none, none, none, st);
+    axis_step<Tc, Tc, double, true, false, false>(F[0], vx, t0, phi, none, none, none, st);
     timing_end(ctx, FVK_STAGE_TRANSFORM, 6);
 }
 
 }  // namespace
 
 void tpf_solve(fvk_ctx *ctx, const double *b, double *phi, bool fp32, hipStream_t st) {
+    const Workspace &w = ctx->ws;
     if (fp32) {
-        const float *E[3] = {ctx->ws.E32[0], ctx->ws.E32[1], ctx->ws.E32[2]};
-        const float *Ei[3] = {ctx->ws.Einv32[0], ctx->ws.Einv32[1], ctx->ws.Einv32[2]};
-        const float *L[3] = {ctx->ws.lam32[0], ctx->ws.lam32[1], ctx->ws.lam32[2]};
-        tpf_typed<float>(ctx, b, phi, E, Ei, L, st);
+        AxisFactors<float> F[3];
+        for (int a = 0; a < 3; ++a) {
+            const bool sym = ctx->n[a] <= kSymMax;
+            F[a] = {sym ? w.Ah32[a] : w.Einv32[a], sym ? w.Bh32[a] : w.E32[a],
+                    sym ? w.lamp32[a] : w.lam32[a], sym};
+        }
+        tpf_typed<float>(ctx, b, phi, F, st);
     } else {
-        const double *E[3] = {ctx->ws.E[0], ctx->ws.E[1], ctx->ws.E[2]};
-        const double *Ei[3] = {ctx->ws.Einv[0], ctx->ws.Einv[1], ctx->ws.Einv[2]};
-        const double *L[3] = {ctx->ws.lam[0], ctx->ws.lam[1], ctx->ws.lam[2]};
-        tpf_typed<double>(ctx, b, phi, E, Ei, L, st);
+        AxisFactors<double> F[3];
+        for (int a = 0; a < 3; ++a) {
+            const bool sym = ctx->n[a] <= kSymMax;
+            F[a] = {sym ? w.Ah[a] : w.Einv[a], sym ? w.Bh[a] : w.E[a],
+                    sym ? w.lamp[a] : w.lam[a], sym};
+        }
+        tpf_typed<double>(ctx, b, phi, F, st);
     }
 }
 

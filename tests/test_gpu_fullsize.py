@@ -15,11 +15,11 @@ TOL = 1e-10
 
 
 def host_divergence(ctx, y):
-    """max |D v| over the cells, in NumPy, with the library's face coordinates."""
+    """max |D v| over the cells, in NumPy, with the library's cell widths."""
     import numpy as np
     v = y.cpu().numpy()
     nx, ny, nz = ctx.n
-    hx, hy, hz = (np.diff(ctx.axis(a)[0]) for a in range(3))
+    hx, hy, hz = (ctx.axis(a)[2][1:-1] for a in range(3))
     d = ((v[0, 1:-1, 1:-1, 1:nx + 1] - v[0, 1:-1, 1:-1, 0:nx]) / hx[None, None, :]
          + (v[1, 1:-1, 1:ny + 1, 1:-1] - v[1, 1:-1, 0:ny, 1:-1]) / hy[None, :, None]
          + (v[2, 1:nz + 1, 1:-1, 1:-1] - v[2, 0:nz, 1:-1, 1:-1]) / hz[:, None, None])
