@@ -57,10 +57,20 @@ struct AxisView {
     int n0;      // extent of the fastest column index
     long s0, s1; // strides of the two column indices
     int ncols;   // n0 * n1
+    unsigned long long m0;   // 2^40 / n0 + 1: c / n0 == (c * m0) >> 40 for c n0 < 2^40
 };
 
+inline AxisView axis_view(int na, long sb, int n0, long s0, long s1, int ncols) {
+    return AxisView{na, sb, n0, s0, s1, ncols, (1ull << 40) / unsigned(n0) + 1};
+}
+
+// column c -> (c / n0, c % n0) by a multiply-shift (no integer division)
+__device__ __forceinline__ int col_hi(const AxisView &v, int c) {
+    return int((unsigned long long)(unsigned)c * v.m0 >> 40);
+}
 __device__ __forceinline__ long col_addr(const AxisView &v, int c) {
-    return long(c / v.n0) * v.s1 + long(c % v.n0) * v.s0;
+    const int hi = col_hi(v, c);
+    return long(hi) * v.s1 + long(c - hi * v.n0) * v.s0;
 }
 
 // Y = M applied along one axis of X.  Block tile: TM output rows x TN
@@ -126,7 +136,8 @@ __global__ __launch_bounds__(NT) void k_axis(const Tc *__restrict__ M, AxisView 
             if (row >= na) continue;
             Tc val = acc[r];
             if (SCALE) {
-                const Tc l = lamR[row] + lam0[col % v.n0] + lam1[col / v.n0];
+                const int ch = col_hi(v, col);
+                const Tc l = lamR[row] + lam0[col - ch * v.n0] + lam1[ch];
                 val = (row == 0 && col == 0) ? Tc(0) : val / l;
             }
             Y[ca + long(row) * v.sb] = Tout(val);
@@ -299,7 +310,8 @@ __global__ __launch_bounds__(64 * NW) void k_axis_sym(const Tc *__restrict__ M, 
             if (FWD) {
                 Tc ve = pe, vo = po;
                 if (SCALE) {
-                    const Tc l01 = lam0[pp % v.n0] + lam1[pp / v.n0];
+                    const int ph = col_hi(v, pp);
+                    const Tc l01 = lam0[pp - ph * v.n0] + lam1[ph];
                     ve = (t == 0 && pp == 0) ? Tc(0) : pe * recip(lamR[t] + l01);
                     if (t < no) vo = po * recip(lamR[ne + t] + l01);
                 }
@@ -480,7 +492,8 @@ __global__ __launch_bounds__(64 * NW) void k_axis_res(const Tc *__restrict__ M, 
                 if (FWD) {
                     Tc ve = pe, vo = po;
                     if (SCALE) {
-                        const Tc l01 = lam0[pp % v.n0] + lam1[pp / v.n0];
+                        const int ph = col_hi(v, pp);
+                    const Tc l01 = lam0[pp - ph * v.n0] + lam1[ph];
                         ve = (t == 0 && pp == 0) ? Tc(0) : pe * recip(lamR[t] + l01);
                         if (t < no) vo = po * recip(lamR[ne + t] + l01);
                     }
@@ -559,9 +572,9 @@ void tpf_typed(fvk_ctx *ctx, const double *b, double *phi, const AxisFactors<Tc>
     const long pl = long(nx) * ny;
     // axis x: rows i, columns (k, j); axis y: rows j, columns (k, i);
     // axis z: rows k, columns (j, i)
-    const AxisView vx{nx, 1, ny, nx, pl, ny * nz};
-    const AxisView vy{ny, nx, nx, 1, pl, nx * nz};
-    const AxisView vz{nz, pl, nx, 1, nx, nx * ny};
+    const AxisView vx = axis_view(nx, 1, ny, nx, pl, ny * nz);
+    const AxisView vy = axis_view(ny, nx, nx, 1, pl, nx * nz);
+    const AxisView vz = axis_view(nz, pl, nx, 1, nx, nx * ny);
     Tc *t0 = static_cast<Tc *>(ctx->ws.tb0);
     Tc *t1 = static_cast<Tc *>(ctx->ws.tb1);
     const Tc *none = nullptr;
