@@ -114,8 +114,9 @@ fvk_status fv_jacvec(fvk_ctx *ctx, const double *base, const double *x, double *
 
 /* y = P x (transpose = 0): the SIMPLE projection of the velocity part
  * (eq. (13): divergence-free, homogeneous no-slip) and the temperature
- * projection of eq. (21) (homogeneous thermal BCs); y = P^T x (transpose = 1).
- * x == y is allowed. */
+ * projection of eq. (21) (homogeneous thermal BCs); y = P^T x (transpose = 1),
+ * computed as W P W^-1 (W = face control volumes) with the fixed pass count
+ * (one in FP64, two in mixed precision).  x == y is allowed. */
 fvk_status fvk_project(fvk_ctx *ctx, const double *x, double *y, int transpose);
 
 /* The next Krylov vector, eqs (11)-(13): y = A x = P J x (transpose = 0) or
@@ -124,12 +125,15 @@ fvk_status fvk_project(fvk_ctx *ctx, const double *x, double *y, int transpose);
  * correction.  If `passes` or `max_div` is non-NULL the call synchronises and
  * reports the SIMPLE pass count and the final max |D v|; if both are NULL the
  * call is asynchronous and the divergence check is recorded on the device
- * (fvk_simple_stats).  Returns FVK_ENOCONV when the pass cap is hit.
+ * (fvk_simple_stats).  Returns FVK_ENOCONV when the pass cap is hit.  The
+ * transposed call always runs the fixed pass count (its internal divergence,
+ * of W^-1 x, is reported but not tested and not recorded).
  * x and y must not overlap. */
 fvk_status simple_krylov_vec(fvk_ctx *ctx, const double *base, const double *x, double *y,
                              double *p_out, int transpose, int *passes, double *max_div);
-/* Largest max |D v| seen by asynchronous calls since the last query, and the
- * number of such calls that needed more passes than the fixed count. Resets. */
+/* Largest max |D v| seen by asynchronous forward calls since the last query,
+ * and the number of such calls that needed more passes than the fixed count.
+ * Resets. */
 fvk_status fvk_simple_stats(fvk_ctx *ctx, double *max_div, int *n_unconverged);
 
 /* One Arnoldi step on A (or A^T): V holds j+1 orthonormal 4-field vectors

@@ -106,34 +106,52 @@ fvk_status write_coefs(fvk_ctx *ctx, const double *host, size_t count) {
 }
 
 // ---- SIMPLE loop (Sec. 3.1, steps 1-3) ------------------------------------
-// vin: 3 velocity fields with zero wall entries (the momentum predictor);
-// vout: result (3 fields).  vin is clobbered when more than one pass runs.
-// sync: adaptive loop with a host check per pass; otherwise a fixed number of
-// passes and the divergence test is recorded on the device.
-fvk_status simple_forward(fvk_ctx *ctx, double *vin, double *vout, double *p_out, bool sync,
-                          int *passes_out, double *div_out) {
+// vin: 3 velocity fields (the momentum predictor; its wall entries are not
+// read); vout: result (3 fields); spare: a third 3-field buffer for the
+// ping-pong of later passes (it may be vin when vin may be clobbered; it must
+// differ from vout).  sync: adaptive loop with a host check per pass;
+// otherwise a fixed number of passes and the divergence test is recorded on
+// the device.  transposed: the transposed projection W P W^-1 (P is
+// W-orthogonal, W = face control volumes): the first pass reads W^-1 vin and
+// the result is scaled by W, fused into the kernels where the pass count is
+// known in advance.
+fvk_status simple_forward(fvk_ctx *ctx, const double *vin, double *vout, double *spare,
+                          double *p_out, bool sync, int *passes_out, double *div_out,
+                          bool transposed = false) {
     const Geo &g = ctx->geo;
     Workspace &w = ctx->ws;
     hipStream_t st = ctx->stream;
     const bool fp32 = ctx->prec == FVK_MIXED;
     const int fixed = fp32 ? ctx->mixed_passes : 1;
+    // the transposed loop always runs the fixed pass count: its divergence is
+    // that of the internal field W^-1 y, whose size (and rounding floor) has
+    // no relation to the absolute tolerance of the physical velocity;
+    // passes/div are still reported
+    const bool want_div = sync;
+    if (transposed) sync = false;
     if (p_out) launch_fill(p_out, 0.0, ctx->ncell, st);
     timing_begin(ctx, FVK_STAGE_DIV);
-    launch_div(g, vin, w.div, st);
+    launch_div(g, vin, w.div, st, transposed);
     timing_end(ctx, FVK_STAGE_DIV);
-    double *src = vin, *dst = vout;
+    const double *src = vin;
+    double *dst = vout, *other = spare;
     int k = 0;
     double dmax = 0.0;
+    bool scaled_out = false;
     while (true) {
         tpf_solve(ctx, w.div, w.phi, fp32, st);
         const bool last_fixed = !sync && k + 1 >= fixed;
+        const bool win = transposed && k == 0, wout = transposed && last_fixed;
         timing_begin(ctx, FVK_STAGE_CORRECT);
-        launch_correct_oop(g, src, dst, w.phi, p_out, w.div, w.red, st);
+        launch_correct_oop(g, src, dst, w.phi, p_out, w.div, w.red, st, win, wout);
+        // the running record of asynchronous calls covers forward projections
+        const bool record = last_fixed && !transposed;
         launch_max_reduce(w.red, correct_blocks(g), w.div_slots,
-                          last_fixed ? w.div_slots + 1 : nullptr,
-                          last_fixed ? w.dev_counters : nullptr, ctx->simple_tol, st);
+                          record ? w.div_slots + 1 : nullptr, record ? w.dev_counters : nullptr,
+                          ctx->simple_tol, st);
         timing_end(ctx, FVK_STAGE_CORRECT);
         CHECK_LAUNCH(ctx);
+        scaled_out = wout;
         if (sync) {
             fvk_status s = read_back(ctx, w.div_slots, &dmax, 1);
             if (s != FVK_OK) return s;
@@ -144,10 +162,16 @@ fvk_status simple_forward(fvk_ctx *ctx, double *vin, double *vout, double *p_out
         } else if (k >= fixed) {
             break;
         }
-        std::swap(src, dst);
+        src = dst;
+        std::swap(dst, other);
     }
     if (dst != vout) launch_copy(vout, dst, size_t(3) * g.F, st);
+    if (transposed && !scaled_out) launch_face_scale(g, vout, vout, 0, st);
     CHECK_LAUNCH(ctx);
+    if (want_div && !sync) {
+        fvk_status s = read_back(ctx, w.div_slots, &dmax, 1);
+        if (s != FVK_OK) return s;
+    }
     if (passes_out) *passes_out = k;
     if (div_out) *div_out = dmax;
     if (sync && !(dmax < ctx->simple_tol))
@@ -155,21 +179,13 @@ fvk_status simple_forward(fvk_ctx *ctx, double *vin, double *vout, double *p_out
     return FVK_OK;
 }
 
-// Transposed SIMPLE projection of a velocity part: z = P^T y = W P W^-1 y
-// (P is W-orthogonal, W = face control volumes), so the transposed loop is
-// the forward loop -- including its FP32 solves with FP64 refinement in mixed
-// mode -- between two diagonal scalings.  y is not modified; z may be any
-// 3-field buffer except ws.vtmp2.
+// Transposed SIMPLE projection of a velocity part: z = P^T y = W P W^-1 y,
+// i.e. the forward loop -- including its FP32 solves with FP64 refinement in
+// mixed mode -- between two diagonal scalings, fused into its first and last
+// pass.  y is not modified; z may be any 3-field buffer except ws.vtmp2.
 fvk_status simple_transpose(fvk_ctx *ctx, const double *y, double *z, bool sync,
                             int *passes_out, double *div_out) {
-    const Geo &g = ctx->geo;
-    Workspace &w = ctx->ws;
-    launch_face_scale(g, y, w.vtmp2, 1, ctx->stream);
-    CHECK_LAUNCH(ctx);
-    fvk_status s = simple_forward(ctx, w.vtmp2, z, nullptr, sync, passes_out, div_out);
-    launch_face_scale(g, z, z, 0, ctx->stream);
-    CHECK_LAUNCH(ctx);
-    return s;
+    return simple_forward(ctx, y, z, ctx->ws.vtmp2, nullptr, sync, passes_out, div_out, true);
 }
 
 }  // namespace
@@ -500,7 +516,7 @@ fvk_status fvk_project(fvk_ctx *ctx, const double *x, double *y, int transpose) 
         CHECK_LAUNCH(ctx);
         int passes = 0;
         double dmax = 0.0;
-        fvk_status s = simple_forward(ctx, w.vtmp, y, nullptr, true, &passes, &dmax);
+        fvk_status s = simple_forward(ctx, w.vtmp, y, w.vtmp, nullptr, true, &passes, &dmax);
         launch_copy(y + 3 * F, w.vtmp + 3 * F, F, st);
         CHECK_LAUNCH(ctx);
         return s;
@@ -533,7 +549,7 @@ fvk_status simple_krylov_vec(fvk_ctx *ctx, const double *base, const double *x, 
         const bool sync = passes || max_div;
         int k = 0;
         double dmax = 0.0;
-        fvk_status s = simple_forward(ctx, w.vtmp, y, p_out, sync, &k, &dmax);
+        fvk_status s = simple_forward(ctx, w.vtmp, y, w.vtmp, p_out, sync, &k, &dmax);
         if (passes) *passes = k;
         if (max_div) *max_div = dmax;
         return s;

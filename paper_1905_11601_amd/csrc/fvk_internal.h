@@ -137,11 +137,12 @@ void launch_jacvec_T(const Geo &g, Coefs c, int span_aa, int fold_ext, const dou
                      const double *yvel, const double *yT, double *x, hipStream_t st);
 void launch_residual(const Geo &g, Coefs c, int span_aa, const double *base, double *F,
                      hipStream_t st);
-void launch_div(const Geo &g, const double *v, double *div, hipStream_t st);
+void launch_div(const Geo &g, const double *v, double *div, hipStream_t st, bool win = false);
 // v_out = v_in - G phi (wall entries 0), p_out += phi, div_out = D v_out,
 // block maxima of |D v_out| to red[0 .. correct_blocks)
 void launch_correct_oop(const Geo &g, const double *vin, double *vout, const double *phi,
-                        double *p_out, double *div_out, double *red, hipStream_t st);
+                        double *p_out, double *div_out, double *red, hipStream_t st,
+                        bool win = false, bool wout = false);
 int correct_blocks(const Geo &g);
 // interior velocity faces scaled by W = d_A h_B h_C (inverse: by 1/W), rest 0
 void launch_face_scale(const Geo &g, const double *src, double *dst, int inverse,

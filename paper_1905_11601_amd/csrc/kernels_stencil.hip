@@ -19,6 +19,27 @@ namespace {
 
 constexpr int BX = 64, BY = 4;
 
+// XCD-aware block order for the per-point kernels: hardware block b runs on
+// XCD b % 8, so consecutive blocks (one z-plane) would spread every plane over
+// all eight L2s; give each XCD a contiguous range of logical blocks instead,
+// so the neighbouring planes a block reads sit in its own L2.
+struct Blk {
+    int x, y, z;
+    long lin;   // logical linear index (unique per block)
+};
+__device__ __forceinline__ Blk xcd_block() {
+    const int nbx = gridDim.x, nby = gridDim.y;
+    const long nb = long(nbx) * nby * gridDim.z;
+    const long b = (long(blockIdx.z) * nby + blockIdx.y) * nbx + blockIdx.x;
+    const long lb = (nb % 8) == 0 ? (b % 8) * (nb / 8) + b / 8 : b;
+    Blk r;
+    r.lin = lb;
+    r.x = int(lb % nbx);
+    r.y = int((lb / nbx) % nby);
+    r.z = int(lb / (long(nbx) * nby));
+    return r;
+}
+
 __device__ __forceinline__ bool face_row(const Geo &g, int A, int i, int j, int k) {
     const int idx[3] = {i, j, k};
 #pragma unroll
@@ -33,9 +54,6 @@ __device__ __forceinline__ bool cell_row(const Geo &g, int i, int j, int k) {
     return i >= 1 && i <= g.n[0] && j >= 1 && j <= g.n[1] && k >= 1 && k <= g.n[2];
 }
 
-__device__ __forceinline__ bool in_box(const Geo &g, int i, int j, int k) {
-    return i >= 0 && i < g.np[0] && j >= 0 && j < g.np[1] && k >= 0 && k < g.np[2];
-}
 
 __device__ __forceinline__ long pos(const Geo &g, int i, int j, int k) {
     return (long(k) * g.np[1] + j) * g.np[0] + i;
@@ -134,9 +152,10 @@ __global__ __launch_bounds__(BX *BY) void k_jac(Geo g, Coefs c, int span_aa,
                                                 const double *__restrict__ x,
                                                 double *__restrict__ yv,
                                                 double *__restrict__ yT) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
+    const Blk B = xcd_block();
+    const int i = B.x * BX + threadIdx.x;
+    const int j = B.y * BY + threadIdx.y;
+    const int k = B.z;
     if (i >= g.np[0] || j >= g.np[1] || k >= g.np[2]) return;
     const long F = g.F;
     const long p = pos(g, i, j, k);
@@ -421,136 +440,180 @@ __global__ __launch_bounds__(TX *TY, 2) void k_jac_tiled(Geo g, Coefs c, int spa
 
 // ---------------------------------------------------------------- transpose
 
-__device__ __forceinline__ double ld(const Geo &g, const double *f, int i, int j, int k) {
-    return in_box(g, i, j, k) ? f[pos(g, i, j, k)] : 0.0;
-}
-
-// Y restricted to the rows of the momentum equation of component A.
-__device__ __forceinline__ double yv(const Geo &g, int A, const double *Y, int i, int j, int k) {
-    return face_row(g, A, i, j, k) ? Y[pos(g, i, j, k)] : 0.0;
-}
-
-// Y restricted to energy rows; with fold, the insulated-wall entries are added
-// to their neighbours (transpose of the boundary-local extension Ext_T).
-__device__ __forceinline__ double yt(const Geo &g, int fold, const double *Y, int i, int j, int k) {
-    if (!cell_row(g, i, j, k)) return 0.0;
-    const long p = pos(g, i, j, k);
-    double r = Y[p];
-    if (fold) {
-        if (j == 1) r += Y[p - g.s[1]];
-        if (j == g.n[1]) r += Y[p + g.s[1]];
-    }
-    return r;
-}
+// Transposed rows, written once over an accessor X of eight staged fields:
+// 0..2 the momentum rows of Y restricted to the interior A-faces, 3 the energy
+// rows of Y restricted to the cells (folded: with the insulated-wall
+// extension, the wall entries added to their neighbours -- the transpose of
+// Ext_T), 4..6 the base velocity U, 7 the base temperature Theta (zero
+// outside the stored box).  X.at<d>(f) is field f at offset d.
 
 // Transposed momentum-variable output for component A at stored position
 // (i, j, k): collects every row in which x_A at this position appears, using
 // the flux-adjoint form g = (row differences of Y) of each flux.
-template <int A>
-__device__ double jacT_vel(const Geo &g, Coefs c, const int *idx, const double *const *U,
-                           const double *Th, const double *const *Yv, const double *YT,
-                           int fold) {
-    const int i = idx[0], j = idx[1], k = idx[2];
+template <int A, class Acc>
+__device__ __forceinline__ double jt_vel(const Geo &g, Coefs c, const int *idx, const Acc &X) {
     const AxisDev &aA = g.ax[A];
     const int ia = idx[A];
-    int eA[3] = {0, 0, 0};
-    eA[A] = 1;
-    const double yc = yv(g, A, Yv[A], i, j, k);
-    const double ym = yv(g, A, Yv[A], i - eA[0], j - eA[1], k - eA[2]);
-    const double yp = yv(g, A, Yv[A], i + eA[0], j + eA[1], k + eA[2]);
+    const double yc = AT1(X, A, A, 0), ym = AT1(X, A, A, -1), yp = AT1(X, A, A, 1);
     // viscous, normal direction
     double lapT = -(aA.ih[ia + 1] + aA.ih[ia]) * aA.id[ia] * yc + aA.ih[ia] * aA.id[ia - 1] * ym +
                   aA.ih[ia + 1] * aA.id[ia + 1] * yp;
     // advection, normal direction: - [Ubar(c=ia) gn(ia) + Ubar(c=ia+1) gn(ia+1)]
-    const double uc = ld(g, U[A], i, j, k);
-    const double um = ld(g, U[A], i - eA[0], j - eA[1], k - eA[2]);
-    const double up = ld(g, U[A], i + eA[0], j + eA[1], k + eA[2]);
+    const double uc = AT1(X, 4 + A, A, 0), um = AT1(X, 4 + A, A, -1), up = AT1(X, 4 + A, A, 1);
     double advT = 0.5 * (um + uc) * (ym * aA.id[ia - 1] - yc * aA.id[ia]) +
                   0.5 * (uc + up) * (yc * aA.id[ia] - yp * aA.id[ia + 1]);
     const double wa = aA.w[ia];
-#pragma unroll
-    for (int t = 1; t <= 2; ++t) {
-        const int Bt = (A + t) % 3;
-        const AxisDev &aB = g.ax[Bt];
-        const int jb = idx[Bt];
-        int eB[3] = {0, 0, 0};
-        eB[Bt] = 1;
-        const double ymB = yv(g, A, Yv[A], i - eB[0], j - eB[1], k - eB[2]);
-        const double ypB = yv(g, A, Yv[A], i + eB[0], j + eB[1], k + eB[2]);
-        lapT += -(aB.id[jb] + aB.id[jb - 1]) * aB.ih[jb] * yc + aB.id[jb - 1] * aB.ih[jb - 1] * ymB +
-                aB.id[jb] * aB.ih[jb + 1] * ypB;
-        // U_Bt interpolated along A to this A-face, at Bt-faces jb and jb-1
-        const double ut_p = (1.0 - wa) * ld(g, U[Bt], i, j, k) +
-                            wa * ld(g, U[Bt], i + eA[0], j + eA[1], k + eA[2]);
-        const double ut_m = (1.0 - wa) * ld(g, U[Bt], i - eB[0], j - eB[1], k - eB[2]) +
-                            wa * ld(g, U[Bt], i + eA[0] - eB[0], j + eA[1] - eB[1], k + eA[2] - eB[2]);
-        // (3) x_A transported in the A-rows along Bt
-        const double gt_p = yc * aB.ih[jb] - ypB * aB.ih[jb + 1];
-        const double gt_m = ymB * aB.ih[jb - 1] - yc * aB.ih[jb];
-        advT += ut_p * (1.0 - aB.w[jb]) * gt_p + ut_m * aB.w[jb - 1] * gt_m;
-        // (4) x_A transporting U_Bt in the Bt-rows along A
-        const double ybc = yv(g, Bt, Yv[Bt], i, j, k);
-        const double ybA = yv(g, Bt, Yv[Bt], i + eA[0], j + eA[1], k + eA[2]);
-        const double ybm = yv(g, Bt, Yv[Bt], i - eB[0], j - eB[1], k - eB[2]);
-        const double ybmA = yv(g, Bt, Yv[Bt], i - eB[0] + eA[0], j - eB[1] + eA[1], k - eB[2] + eA[2]);
-        const double gq_p = ybc * aA.ih[ia] - ybA * aA.ih[ia + 1];
-        const double gq_m = ybm * aA.ih[ia] - ybmA * aA.ih[ia + 1];
-        advT += (1.0 - aB.w[jb]) * ut_p * gq_p + aB.w[jb - 1] * ut_m * gq_m;
+#define FVK_JT_TANGENTIAL(Bt)                                                                \
+    {                                                                                        \
+        const AxisDev &aB = g.ax[Bt];                                                        \
+        const int jb = idx[Bt];                                                              \
+        const double ymB = AT1(X, A, Bt, -1), ypB = AT1(X, A, Bt, 1);                        \
+        lapT += -(aB.id[jb] + aB.id[jb - 1]) * aB.ih[jb] * yc +                              \
+                aB.id[jb - 1] * aB.ih[jb - 1] * ymB + aB.id[jb] * aB.ih[jb + 1] * ypB;        \
+        /* U_Bt interpolated along A to this A-face, at Bt-faces jb and jb-1 */              \
+        const double ut_p = (1.0 - wa) * AT1(X, 4 + Bt, A, 0) + wa * AT1(X, 4 + Bt, A, 1);   \
+        const double ut_m =                                                                  \
+            (1.0 - wa) * AT1(X, 4 + Bt, Bt, -1) + wa * AT2(X, 4 + Bt, A, 1, Bt, -1);         \
+        /* (3) x_A transported in the A-rows along Bt */                                     \
+        const double gt_p = yc * aB.ih[jb] - ypB * aB.ih[jb + 1];                            \
+        const double gt_m = ymB * aB.ih[jb - 1] - yc * aB.ih[jb];                            \
+        advT += ut_p * (1.0 - aB.w[jb]) * gt_p + ut_m * aB.w[jb - 1] * gt_m;                 \
+        /* (4) x_A transporting U_Bt in the Bt-rows along A */                               \
+        const double ybc = AT1(X, Bt, A, 0), ybA = AT1(X, Bt, A, 1);                         \
+        const double ybm = AT1(X, Bt, Bt, -1), ybmA = AT2(X, Bt, A, 1, Bt, -1);              \
+        const double gq_p = ybc * aA.ih[ia] - ybA * aA.ih[ia + 1];                           \
+        const double gq_m = ybm * aA.ih[ia] - ybmA * aA.ih[ia + 1];                          \
+        advT += (1.0 - aB.w[jb]) * ut_p * gq_p + aB.w[jb - 1] * ut_m * gq_m;                 \
     }
+    FVK_JT_TANGENTIAL((A + 1) % 3)
+    FVK_JT_TANGENTIAL((A + 2) % 3)
+#undef FVK_JT_TANGENTIAL
     // (5) x_A transporting Theta in the energy rows
-    const double thf = (1.0 - wa) * ld(g, Th, i, j, k) + wa * ld(g, Th, i + eA[0], j + eA[1], k + eA[2]);
-    const double tc = yt(g, fold, YT, i, j, k);
-    const double tp = yt(g, fold, YT, i + eA[0], j + eA[1], k + eA[2]);
+    const double thf = (1.0 - wa) * AT1(X, 7, A, 0) + wa * AT1(X, 7, A, 1);
+    const double tc = AT1(X, 3, A, 0), tp = AT1(X, 3, A, 1);
     advT += thf * (tc * aA.ih[ia] - tp * aA.ih[ia + 1]);
     return c.nu * lapT - advT;
 }
 
-__device__ double jacT_temp(const Geo &g, Coefs c, const int *idx, const double *const *U,
-                            const double *Yw, const double *YT, int fold) {
-    const int i = idx[0], j = idx[1], k = idx[2];
-    const double tc = yt(g, fold, YT, i, j, k);
+template <int A, class Acc>
+__device__ __forceinline__ void jt_temp_axis(const Geo &g, const int *idx, const Acc &X,
+                                             double tc, double &lapT, double &advT) {
+    const AxisDev &aA = g.ax[A];
+    const int ia = idx[A];
+    const double tm = AT1(X, 3, A, -1), tp = AT1(X, 3, A, 1);
+    lapT += -(aA.id[ia] + aA.id[ia - 1]) * aA.ih[ia] * tc + aA.id[ia - 1] * aA.ih[ia - 1] * tm +
+            aA.id[ia] * aA.ih[ia + 1] * tp;
+    const double uq = AT1(X, 4 + A, A, 0), uqm = AT1(X, 4 + A, A, -1);
+    const double g_p = tc * aA.ih[ia] - tp * aA.ih[ia + 1];
+    const double g_m = tm * aA.ih[ia - 1] - tc * aA.ih[ia];
+    advT += uq * (1.0 - aA.w[ia]) * g_p + uqm * aA.w[ia - 1] * g_m;
+}
+
+template <class Acc>
+__device__ __forceinline__ double jt_temp(const Geo &g, Coefs c, const int *idx, const Acc &X) {
+    const double tc = AT1(X, 3, 0, 0);
     double lapT = 0.0, advT = 0.0;
-#pragma unroll
-    for (int A = 0; A < 3; ++A) {
-        const AxisDev &aA = g.ax[A];
-        const int ia = idx[A];
-        int e[3] = {0, 0, 0};
-        e[A] = 1;
-        const double tm = yt(g, fold, YT, i - e[0], j - e[1], k - e[2]);
-        const double tp = yt(g, fold, YT, i + e[0], j + e[1], k + e[2]);
-        lapT += -(aA.id[ia] + aA.id[ia - 1]) * aA.ih[ia] * tc + aA.id[ia - 1] * aA.ih[ia - 1] * tm +
-                aA.id[ia] * aA.ih[ia + 1] * tp;
-        const double uq = ld(g, U[A], i, j, k);
-        const double uqm = ld(g, U[A], i - e[0], j - e[1], k - e[2]);
-        const double g_p = tc * aA.ih[ia] - tp * aA.ih[ia + 1];
-        const double g_m = tm * aA.ih[ia - 1] - tc * aA.ih[ia];
-        advT += uq * (1.0 - aA.w[ia]) * g_p + uqm * aA.w[ia - 1] * g_m;
-    }
+    jt_temp_axis<0>(g, idx, X, tc, lapT, advT);
+    jt_temp_axis<1>(g, idx, X, tc, lapT, advT);
+    jt_temp_axis<2>(g, idx, X, tc, lapT, advT);
     // buoyancy: the w-rows read T at the z-centres k and k+1
     const AxisDev &az = g.ax[2];
-    const double buo = (1.0 - az.w[k]) * yv(g, 2, Yw, i, j, k) + az.w[k - 1] * yv(g, 2, Yw, i, j, k - 1);
+    const int k = idx[2];
+    const double buo = (1.0 - az.w[k]) * AT1(X, 2, 2, 0) + az.w[k - 1] * AT1(X, 2, 2, -1);
     return c.kappa * lapT - advT + c.b * buo;
 }
 
-__global__ __launch_bounds__(BX *BY) void k_jacT(Geo g, Coefs c, int fold,
-                                                 const double *__restrict__ base,
-                                                 const double *__restrict__ yvel,
-                                                 const double *__restrict__ yT,
-                                                 double *__restrict__ x) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
-    if (i >= g.np[0] || j >= g.np[1] || k >= g.np[2]) return;
+// Tiled transposed Jacobian: the same k-march and LDS plane ring as
+// k_jac_tiled, over ALL stored points (outputs live on walls too).  Plane
+// entries are staged already masked (momentum rows on interior faces, energy
+// rows on cells, folded) so the rows read them without tests.  The halo
+// origin is one point below the tile in x and y; planes -1 and nz+2 are zero.
+__global__ __launch_bounds__(TX *TY, 2) void k_jacT_tiled(Geo g, Coefs c, int fold,
+                                                          const double *__restrict__ base,
+                                                          const double *__restrict__ yvel,
+                                                          const double *__restrict__ yT,
+                                                          double *__restrict__ x, int kchunk) {
+    __shared__ double lds[3][NF * PLANE];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+    const Blk B = xcd_block();
+    const int i0 = B.x * TX - 1, j0 = B.y * TY - 1;   // halo origin
+    const int i = i0 + 1 + tx, j = j0 + 1 + ty;
+    const int np2 = g.np[2];
+    const int kb = B.z * kchunk;
+    const int ke = min(np2 - 1, kb + kchunk - 1);
+    const bool act = i < g.np[0] && j < g.np[1];
     const long F = g.F;
-    const long p = pos(g, i, j, k);
-    const int idx[3] = {i, j, k};
-    const double *U[3] = {base, base + F, base + 2 * F};
-    const double *Th = base + 3 * F;
-    const double *Y[3] = {yvel, yvel + F, yvel + 2 * F};
-    x[p] = jacT_vel<0>(g, c, idx, U, Th, Y, yT, fold);
-    x[p + F] = jacT_vel<1>(g, c, idx, U, Th, Y, yT, fold);
-    x[p + 2 * F] = jacT_vel<2>(g, c, idx, U, Th, Y, yT, fold);
-    x[p + 3 * F] = jacT_temp(g, c, idx, U, Y[2], yT, fold);
+    double raw[NF][PER_T], fm[PER_T], fp[PER_T];
+    // loads of plane kk (clamped addresses; masks applied in stage)
+    auto fetch = [&](int kk) {
+        const int kc = min(max(kk, 0), np2 - 1);
+#pragma unroll
+        for (int q = 0; q < PER_T; ++q) {
+            const int r = min(tid + q * NT_T, PLANE - 1);
+            const int gi = min(max(i0 + r % TWP, 0), g.np[0] - 1);
+            const int gj = min(max(j0 + r / TWP, 0), g.np[1] - 1);
+            const long off = pos(g, gi, gj, kc);
+#pragma unroll
+            for (int f = 0; f < 3; ++f) raw[f][q] = yvel[f * F + off];
+            raw[3][q] = yT[off];
+#pragma unroll
+            for (int f = 4; f < NF; ++f) raw[f][q] = base[(f - 4) * F + off];
+            // neighbours for the fold, only on the two rows next to the
+            // insulated walls
+            fm[q] = 0.0;
+            fp[q] = 0.0;
+            if (fold && gj == 1) fm[q] = yT[off - g.s[1]];
+            if (fold && gj == g.n[1]) fp[q] = yT[off + g.s[1]];
+        }
+    };
+    auto stage = [&](int kk, double *dst) {
+#pragma unroll
+        for (int q = 0; q < PER_T; ++q) {
+            const int r = tid + q * NT_T;
+            if (r >= PLANE) continue;
+            const int gi = i0 + r % TWP, gj = j0 + r / TWP;
+            const bool box = gi >= 0 && gi < g.np[0] && gj >= 0 && gj < g.np[1] && kk >= 0 &&
+                             kk < np2;
+#pragma unroll
+            for (int f = 0; f < 3; ++f)
+                dst[f * PLANE + r] = face_row(g, f, gi, gj, kk) ? raw[f][q] : 0.0;
+            double t = 0.0;
+            if (cell_row(g, gi, gj, kk)) {
+                t = raw[3][q];
+                if (fold) {
+                    if (gj == 1) t += fm[q];
+                    if (gj == g.n[1]) t += fp[q];
+                }
+            }
+            dst[3 * PLANE + r] = t;
+#pragma unroll
+            for (int f = 4; f < NF; ++f) dst[f * PLANE + r] = box ? raw[f][q] : 0.0;
+        }
+    };
+    fetch(kb - 1);
+    stage(kb - 1, lds[(kb + 2) % 3]);
+    fetch(kb);
+    stage(kb, lds[kb % 3]);
+    fetch(kb + 1);
+    TileAcc X;
+    X.c = (ty + 1) * TWP + tx + 1;
+    for (int k = kb; k <= ke; ++k) {
+        stage(k + 1, lds[(k + 1) % 3]);
+        lds_barrier();
+        if (k + 1 < ke + 1) fetch(k + 2);
+        if (act) {
+            X.s[0] = lds[(k + 2) % 3];
+            X.s[1] = lds[k % 3];
+            X.s[2] = lds[(k + 1) % 3];
+            const int idx[3] = {i, j, k};
+            const long p = pos(g, i, j, k);
+            x[p] = jt_vel<0>(g, c, idx, X);
+            x[p + F] = jt_vel<1>(g, c, idx, X);
+            x[p + 2 * F] = jt_vel<2>(g, c, idx, X);
+            x[p + 3 * F] = jt_temp(g, c, idx, X);
+        }
+        lds_barrier();
+    }
 }
 
 // ---------------------------------------------------------------- SIMPLE pieces
@@ -560,18 +623,37 @@ __device__ __forceinline__ long cidx(const Geo &g, int i, int j, int k) {
 }
 
 // D v at interior cells (compact output).
+// inverse face control volume 1/W of face A at (i, j, k): (1/d_A)(1/h_B)(1/h_C)
+__device__ __forceinline__ double inv_w(const Geo &g, int A, int i, int j, int k) {
+    const int idx[3] = {i, j, k};
+    const int B = (A + 1) % 3, C = (A + 2) % 3;
+    return g.ax[A].id[idx[A]] * g.ax[B].ih[idx[B]] * g.ax[C].ih[idx[C]];
+}
+
+// WIN: the divergence of W^-1 v (transposed projection), scaling on the fly
+template <bool WIN>
 __global__ __launch_bounds__(BX *BY) void k_div(Geo g, const double *__restrict__ v,
                                                 double *__restrict__ dv) {
-    const int i = blockIdx.x * BX + threadIdx.x + 1;
-    const int j = blockIdx.y * BY + threadIdx.y + 1;
-    const int k = blockIdx.z + 1;
+    const Blk B = xcd_block();
+    const int i = B.x * BX + threadIdx.x + 1;
+    const int j = B.y * BY + threadIdx.y + 1;
+    const int k = B.z + 1;
     if (i > g.n[0] || j > g.n[1] || k > g.n[2]) return;
     const long p = pos(g, i, j, k);
     const int idx[3] = {i, j, k};
     double s = 0.0;
 #pragma unroll
-    for (int A = 0; A < 3; ++A)
-        s += (v[A * g.F + p] - v[A * g.F + p - g.s[A]]) * g.ax[A].ih[idx[A]];
+    for (int A = 0; A < 3; ++A) {
+        double vp = v[A * g.F + p], vm = v[A * g.F + p - g.s[A]];
+        if (WIN) {
+            // wall faces are zero after the scaling (not interior faces)
+            vp = idx[A] < g.n[A] ? vp * inv_w(g, A, i, j, k) : 0.0;
+            vm = idx[A] > 1 ? vm * inv_w(g, A, A == 0 ? i - 1 : i, A == 1 ? j - 1 : j,
+                                         A == 2 ? k - 1 : k)
+                            : 0.0;
+        }
+        s += (vp - vm) * g.ax[A].ih[idx[A]];
+    }
     dv[cidx(g, i, j, k)] = s;
 }
 
@@ -592,70 +674,110 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
 
 // v_out = v_in - G phi on interior faces, p_out += phi, div_out = D v_out, and
 // max |D v_out| over the grid.  Each thread owns the + faces of its cell; the
-// - faces are recomputed from v_in so the kernel is race-free (v_out != v_in).
-// Wall, edge and padding entries of v_out are written 0 (homogeneous no-slip,
+// x and y - faces are recomputed from v_in so the kernel is race-free
+// (v_out != v_in).  A block owns a BX x BY column tile and kchunk consecutive
+// planes, marching up in k: phi at k-1 and k and the corrected - face in z
+// are carried in registers, so each phi and w value is read once.  Wall,
+// edge and padding entries of v_out are written 0 (homogeneous no-slip,
 // SIMPLE step 3) by the threads next to them, so v_out is fully defined.
 // Block maxima of |D v_out| go to red[block]; a one-block kernel reduces them
 // (per-block atomics on one address serialise in L2 and cost far more).
+// WIN: v_in is read as W^-1 v_in (first pass of the transposed projection);
+// WOUT: v_out is written as W v_out (its last pass); D v_out and its maximum
+// are those of the unscaled result.
+template <bool WIN, bool WOUT>
 __global__ __launch_bounds__(BX *BY) void k_correct(Geo g, const double *__restrict__ vin,
                                                     const double *__restrict__ phi,
                                                     double *__restrict__ vout,
                                                     double *__restrict__ p_out,
                                                     double *__restrict__ div_out,
-                                                    double *__restrict__ red) {
+                                                    double *__restrict__ red, int kchunk) {
     __shared__ double sh[8];
-    const int i = blockIdx.x * BX + threadIdx.x + 1;
-    const int j = blockIdx.y * BY + threadIdx.y + 1;
-    const int k = blockIdx.z + 1;
-    double dmax = 0.0;
+    const Blk B = xcd_block();
+    const int i = B.x * BX + threadIdx.x + 1;
+    const int j = B.y * BY + threadIdx.y + 1;
+    const int kb = 1 + B.z * kchunk;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-    if (i <= nx && j <= ny && k <= nz) {
-        const long p = pos(g, i, j, k);
-        const long c = cidx(g, i, j, k);
-        const int idx[3] = {i, j, k};
-        const double ph = phi[c];
-        const long cs[3] = {1, nx, long(nx) * ny};
-        double dv = 0.0;
-#pragma unroll
-        for (int A = 0; A < 3; ++A) {
-            const int ia = idx[A];
-            const double *vi = vin + A * g.F;
-            double vp = 0.0;   // the + face: interior row, or the wall face (0)
-            if (ia <= g.n[A] - 1) vp = vi[p] - (phi[c + cs[A]] - ph) * g.ax[A].id[ia];
-            double vm = 0.0;
-            if (ia >= 2) vm = vi[p - g.s[A]] - (ph - phi[c - cs[A]]) * g.ax[A].id[ia - 1];
-            vout[A * g.F + p] = vp;
-            dv += (vp - vm) * g.ax[A].ih[ia];
+    const int ke = min(nz, kb + kchunk - 1);
+    double dmax = 0.0;
+    if (i <= nx && j <= ny) {
+        const long F = g.F, sxy = long(nx) * ny;
+        const double *vu = vin, *vv = vin + F, *vw = vin + 2 * F;
+        const double idxp = g.ax[0].id[i], idxm = g.ax[0].id[i - 1], ihx = g.ax[0].ih[i];
+        const double idyp = g.ax[1].id[j], idym = g.ax[1].id[j - 1], ihy = g.ax[1].ih[j];
+        // W^-1 factors of this column's faces (x and y faces: times 1/h_z(k))
+        const double iwu = idxp * ihy, iwum = idxm * ihy, iwv = ihx * idyp, iwvm = ihx * idym,
+                     iww = ihx * ihy;
+        long c = cidx(g, i, j, kb);
+        long p = pos(g, i, j, kb);
+        double ph = phi[c];
+        double wm = 0.0;   // corrected w on the - face of the current cell
+        if (kb >= 2) {
+            double w0 = vw[p - g.s[2]];
+            if (WIN) w0 *= iww * g.ax[2].id[kb - 1];
+            wm = w0 - (ph - phi[c - sxy]) * g.ax[2].id[kb - 1];
         }
-        if (p_out) p_out[c] += ph;
-        if (div_out) div_out[c] = dv;
-        dmax = fabs(dv);
-        // zero the velocity wall neighbours this cell owns (the stored entries
-        // with an index 0 or n+1 next to it, including edges and corners)
-        const int lo[3] = {i == 1 ? -1 : 0, j == 1 ? -1 : 0, k == 1 ? -1 : 0};
-        const int hi[3] = {i == nx ? 1 : 0, j == ny ? 1 : 0, k == nz ? 1 : 0};
-        if (lo[0] | lo[1] | lo[2] | hi[0] | hi[1] | hi[2]) {
-            for (int dk = lo[2]; dk <= hi[2]; ++dk)
-                for (int dj = lo[1]; dj <= hi[1]; ++dj)
-                    for (int di = lo[0]; di <= hi[0]; ++di) {
-                        if (di == 0 && dj == 0 && dk == 0) continue;
-                        const long q = pos(g, i + di, j + dj, k + dk);
-                        vout[q] = 0.0;
-                        vout[q + g.F] = 0.0;
-                        vout[q + 2 * g.F] = 0.0;
-                    }
+        for (int k = kb; k <= ke; ++k) {
+            const double ihzk = g.ax[2].ih[k];
+            const double php = k < nz ? phi[c + sxy] : 0.0;
+            double u0 = vu[p], u1 = vu[p - 1], v0 = vv[p], v1 = vv[p - g.s[1]], w0 = vw[p];
+            if (WIN) {
+                u0 *= iwu * ihzk;
+                u1 *= iwum * ihzk;
+                v0 *= iwv * ihzk;
+                v1 *= iwvm * ihzk;
+                w0 *= iww * g.ax[2].id[k];
+            }
+            const double up = i < nx ? u0 - (phi[c + 1] - ph) * idxp : 0.0;
+            const double um = i >= 2 ? u1 - (ph - phi[c - 1]) * idxm : 0.0;
+            const double vp = j < ny ? v0 - (phi[c + nx] - ph) * idyp : 0.0;
+            const double vm = j >= 2 ? v1 - (ph - phi[c - nx]) * idym : 0.0;
+            const double wp = k < nz ? w0 - (php - ph) * g.ax[2].id[k] : 0.0;
+            if (WOUT) {
+                vout[p] = up / (iwu * ihzk);
+                vout[p + F] = vp / (iwv * ihzk);
+                vout[p + 2 * F] = wp / (iww * g.ax[2].id[k]);
+            } else {
+                vout[p] = up;
+                vout[p + F] = vp;
+                vout[p + 2 * F] = wp;
+            }
+            const double dv = (up - um) * ihx + (vp - vm) * ihy + (wp - wm) * g.ax[2].ih[k];
+            if (p_out) p_out[c] += ph;
+            if (div_out) div_out[c] = dv;
+            dmax = fmax(dmax, fabs(dv));
+            // zero the velocity wall neighbours this cell owns (the stored
+            // entries with an index 0 or n+1 next to it, edges and corners)
+            const int lo[3] = {i == 1 ? -1 : 0, j == 1 ? -1 : 0, k == 1 ? -1 : 0};
+            const int hi[3] = {i == nx ? 1 : 0, j == ny ? 1 : 0, k == nz ? 1 : 0};
+            if (lo[0] | lo[1] | lo[2] | hi[0] | hi[1] | hi[2]) {
+                for (int dk = lo[2]; dk <= hi[2]; ++dk)
+                    for (int dj = lo[1]; dj <= hi[1]; ++dj)
+                        for (int di = lo[0]; di <= hi[0]; ++di) {
+                            if (di == 0 && dj == 0 && dk == 0) continue;
+                            const long q = pos(g, i + di, j + dj, k + dk);
+                            vout[q] = 0.0;
+                            vout[q + F] = 0.0;
+                            vout[q + 2 * F] = 0.0;
+                        }
+            }
+            wm = wp;
+            ph = php;
+            c += sxy;
+            p += g.s[2];
         }
     }
     const double r = block_max(dmax, sh);
     if (threadIdx.x == 0 && threadIdx.y == 0)
-        red[(long(blockIdx.z) * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = r;
+        red[B.lin] = r;
 }
 
 // zero-walls copy: dst = src on interior faces, 0 elsewhere (velocity fields)
 __global__ void k_zero_vel_walls(Geo g, const double *__restrict__ src, double *__restrict__ dst) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
+    const Blk B = xcd_block();
+    const int i = B.x * BX + threadIdx.x;
+    const int j = B.y * BY + threadIdx.y;
+    const int k = B.z;
     if (i >= g.np[0] || j >= g.np[1] || k >= g.np[2]) return;
     const long p = pos(g, i, j, k);
 #pragma unroll
@@ -668,9 +790,10 @@ __global__ void k_zero_vel_walls(Geo g, const double *__restrict__ src, double *
 // nodes and edges <- 0, insulated y-wall nodes <- adjacent interior value.
 __global__ void k_ext_T(Geo g, int span_aa, const double *__restrict__ src,
                         double *__restrict__ dst) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
+    const Blk B = xcd_block();
+    const int i = B.x * BX + threadIdx.x;
+    const int j = B.y * BY + threadIdx.y;
+    const int k = B.z;
     if (i >= g.np[0] || j >= g.np[1] || k >= g.np[2]) return;
     const long p = pos(g, i, j, k);
     double r = 0.0;
@@ -690,9 +813,10 @@ __global__ void k_ext_T(Geo g, int span_aa, const double *__restrict__ src,
 // velocity entry.  In place is allowed.
 __global__ void k_face_scale(Geo g, const double *__restrict__ src, double *__restrict__ dst,
                              int inverse) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
+    const Blk B = xcd_block();
+    const int i = B.x * BX + threadIdx.x;
+    const int j = B.y * BY + threadIdx.y;
+    const int k = B.z;
     if (i >= g.np[0] || j >= g.np[1] || k >= g.np[2]) return;
     const long p = pos(g, i, j, k);
     const int idx[3] = {i, j, k};
@@ -712,9 +836,10 @@ __global__ void k_face_scale(Geo g, const double *__restrict__ src, double *__re
 // T part of P^T: transpose of the boundary-local extension.
 __global__ void k_ext_T_T(Geo g, int span_aa, const double *__restrict__ src,
                           double *__restrict__ dst) {
-    const int i = blockIdx.x * BX + threadIdx.x;
-    const int j = blockIdx.y * BY + threadIdx.y;
-    const int k = blockIdx.z;
+    const Blk B = xcd_block();
+    const int i = B.x * BX + threadIdx.x;
+    const int j = B.y * BY + threadIdx.y;
+    const int k = B.z;
     if (i >= g.np[0] || j >= g.np[1] || k >= g.np[2]) return;
     const long p = pos(g, i, j, k);
     double r = 0.0;
@@ -735,8 +860,19 @@ dim3 cell_grid(const Geo &g) {
 
 }  // namespace
 
+// column tiles x k-chunks of the correction kernel: >= ~1024 blocks, chunks
+// of at least 4 planes where the grid allows
+static dim3 correct_grid(const Geo &g, int *kchunk) {
+    const int nbx = (g.n[0] + BX - 1) / BX, nby = (g.n[1] + BY - 1) / BY;
+    int nchunk = (1024 + nbx * nby - 1) / (nbx * nby);
+    nchunk = std::max(1, std::min(nchunk, std::max(1, g.n[2] / 4)));
+    const int kc = (g.n[2] + nchunk - 1) / nchunk;
+    if (kchunk) *kchunk = kc;
+    return dim3(nbx, nby, (g.n[2] + kc - 1) / kc);
+}
+
 int correct_blocks(const Geo &g) {
-    dim3 gr = cell_grid(g);
+    dim3 gr = correct_grid(g, nullptr);
     return int(gr.x * gr.y * gr.z);
 }
 
@@ -761,16 +897,37 @@ void launch_residual(const Geo &g, Coefs c, int span_aa, const double *base, dou
 
 void launch_jacvec_T(const Geo &g, Coefs c, int span_aa, int fold_ext, const double *base,
                      const double *yvel, const double *yT, double *x, hipStream_t st) {
-    k_jacT<<<box_grid(g), dim3(BX, BY), 0, st>>>(g, c, fold_ext && span_aa, base, yvel, yT, x);
+    // tiles of the whole stored plane; k (all np2 planes) split into chunks
+    const int nbx = (g.np[0] + TX - 1) / TX, nby = (g.np[1] + TY - 1) / TY;
+    int nchunk = (512 + nbx * nby - 1) / (nbx * nby);
+    nchunk = std::max(1, std::min(nchunk, std::max(1, g.np[2] / 4)));
+    const int kchunk = (g.np[2] + nchunk - 1) / nchunk;
+    nchunk = (g.np[2] + kchunk - 1) / kchunk;
+    k_jacT_tiled<<<dim3(nbx, nby, nchunk), dim3(TX, TY), 0, st>>>(
+        g, c, fold_ext && span_aa, base, yvel, yT, x, kchunk);
 }
 
-void launch_div(const Geo &g, const double *v, double *div, hipStream_t st) {
-    k_div<<<cell_grid(g), dim3(BX, BY), 0, st>>>(g, v, div);
+void launch_div(const Geo &g, const double *v, double *div, hipStream_t st, bool win) {
+    if (win)
+        k_div<true><<<cell_grid(g), dim3(BX, BY), 0, st>>>(g, v, div);
+    else
+        k_div<false><<<cell_grid(g), dim3(BX, BY), 0, st>>>(g, v, div);
 }
 
 void launch_correct_oop(const Geo &g, const double *vin, double *vout, const double *phi,
-                        double *p_out, double *div_out, double *red, hipStream_t st) {
-    k_correct<<<cell_grid(g), dim3(BX, BY), 0, st>>>(g, vin, phi, vout, p_out, div_out, red);
+                        double *p_out, double *div_out, double *red, hipStream_t st, bool win,
+                        bool wout) {
+    int kchunk = 1;
+    const dim3 gr = correct_grid(g, &kchunk);
+    const dim3 bl(BX, BY);
+    if (win && wout)
+        k_correct<true, true><<<gr, bl, 0, st>>>(g, vin, phi, vout, p_out, div_out, red, kchunk);
+    else if (win)
+        k_correct<true, false><<<gr, bl, 0, st>>>(g, vin, phi, vout, p_out, div_out, red, kchunk);
+    else if (wout)
+        k_correct<false, true><<<gr, bl, 0, st>>>(g, vin, phi, vout, p_out, div_out, red, kchunk);
+    else
+        k_correct<false, false><<<gr, bl, 0, st>>>(g, vin, phi, vout, p_out, div_out, red, kchunk);
 }
 
 void launch_face_scale(const Geo &g, const double *src, double *dst, int inverse,
