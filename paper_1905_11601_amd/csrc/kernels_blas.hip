@@ -10,7 +10,7 @@ namespace fvk {
 namespace {
 
 constexpr int NT = 256;
-constexpr int GROUP = 8;   // vectors per pass of the multi-dot kernel
+constexpr int GROUP = 16;  // vectors per pass of the multi-dot kernel
 
 __device__ __forceinline__ double wave_sum(double v) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -75,6 +75,7 @@ __global__ __launch_bounds__(NT) void k_multiaxpy(double *__restrict__ w, double
     const size_t r = size_t(blockIdx.x) * NT + threadIdx.x;
     if (r >= n) return;
     double s = 0.0;
+#pragma unroll 8
     for (int q = 0; q < m; ++q) s += c[q] * V[size_t(q) * ldv + r];
     w[r] = alpha * w[r] + beta * s;
 }
