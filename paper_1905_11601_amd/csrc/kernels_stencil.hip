@@ -876,15 +876,23 @@ int correct_blocks(const Geo &g) {
     return int(gr.x * gr.y * gr.z);
 }
 
+// k-chunks of the tiled stencils: marches of ~10 planes while that keeps the
+// grid at <= 2048 blocks, else 512 / tiles chunks (at least 2) -- measured on
+// 100^3, 160^3 and 256^3
+static int stencil_chunks(int tiles, int nk) {
+    int nchunk = (nk + 9) / 10;
+    if (long(tiles) * nchunk > 2048) nchunk = std::max(2, 512 / std::max(1, tiles));
+    return std::max(1, std::min(nchunk, nk));
+}
+
 void launch_jacvec(const Geo &g, Coefs c, int span_aa, int ext, const double *base,
                    const double *x, double *yv, double *yT, hipStream_t st) {
     // tiles of the interior plane; k split into chunks so the grid fills the
     // chip (>= ~2 blocks per CU) while each block keeps a long k-march
     const int nbx = (g.n[0] + TX - 1) / TX, nby = (g.n[1] + TY - 1) / TY;
-    int nchunk = (512 + nbx * nby - 1) / (nbx * nby);
-    nchunk = std::max(1, std::min(nchunk, g.n[2] / 4 > 0 ? g.n[2] / 4 : 1));
-    const int kchunk = (g.n[2] + nchunk - 1) / nchunk;
-    nchunk = (g.n[2] + kchunk - 1) / kchunk;
+    const int nchunk0 = stencil_chunks(nbx * nby, g.n[2]);
+    const int kchunk = (g.n[2] + nchunk0 - 1) / nchunk0;
+    const int nchunk = (g.n[2] + kchunk - 1) / kchunk;
     k_jac_tiled<<<dim3(nbx, nby, nchunk), dim3(TX, TY), 0, st>>>(g, c, span_aa && ext, base, x,
                                                                   yv, yT, kchunk);
 }
@@ -899,10 +907,9 @@ void launch_jacvec_T(const Geo &g, Coefs c, int span_aa, int fold_ext, const dou
                      const double *yvel, const double *yT, double *x, hipStream_t st) {
     // tiles of the whole stored plane; k (all np2 planes) split into chunks
     const int nbx = (g.np[0] + TX - 1) / TX, nby = (g.np[1] + TY - 1) / TY;
-    int nchunk = (512 + nbx * nby - 1) / (nbx * nby);
-    nchunk = std::max(1, std::min(nchunk, std::max(1, g.np[2] / 4)));
-    const int kchunk = (g.np[2] + nchunk - 1) / nchunk;
-    nchunk = (g.np[2] + kchunk - 1) / kchunk;
+    const int nchunk0 = stencil_chunks(nbx * nby, g.np[2]);
+    const int kchunk = (g.np[2] + nchunk0 - 1) / nchunk0;
+    const int nchunk = (g.np[2] + kchunk - 1) / kchunk;
     k_jacT_tiled<<<dim3(nbx, nby, nchunk), dim3(TX, TY), 0, st>>>(
         g, c, fold_ext && span_aa, base, yvel, yT, x, kchunk);
 }
