@@ -101,14 +101,26 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": COPY_BYTES, "launches": 3}))
 
 
+def _forms_divergence(kernel_name):
+    """True for the x-axis transform instances that read the velocity fields
+    and form the divergence (last template argument 1 or 2): they belong to
+    the divergence stage, not to the plain transforms."""
+    if "k_axis_sym<" not in kernel_name:
+        return False
+    head = kernel_name[kernel_name.index("k_axis_sym<") + len("k_axis_sym<"):]
+    args = head[:head.index(">")].split(",")
+    return len(args) == 9 and args[-1].strip() != "0"
+
+
 def _pmc_rows(folder, counter, name_part):
-    """Per-dispatch values (bytes) of `counter` for kernels whose name
-    contains name_part, from a rocprofv3 --pmc csv folder (values in KiB)."""
+    """Per-dispatch values (bytes) of `counter` for the plain transforms whose
+    name contains name_part, from a rocprofv3 --pmc csv folder (values in KiB)."""
     out = []
     for path in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
         with open(path) as f:
             for row in csv.DictReader(f):
-                if row["Counter_Name"] == counter and name_part in row["Kernel_Name"]:
+                if (row["Counter_Name"] == counter and name_part in row["Kernel_Name"]
+                        and not _forms_divergence(row["Kernel_Name"])):
                     out.append(float(row["Counter_Value"]) * 1024.0)
     return out
 

@@ -151,10 +151,12 @@ fvk_status arnoldi_step(fvk_ctx *ctx, const double *base, double *V, size_t ldv,
 /* Stages of the Krylov-vector path timed with HIP events on the context's
  * stream when tracing is on: the Jacobian stencil (forward or transposed,
  * including the fused temperature projection), the divergence of the momentum
- * predictor, the axis transforms of the TPF Poisson solve (one event pair
- * around the six back-to-back launches of a solve, counted as six launches),
- * the velocity correction with its fused divergence check, and the
- * Gram-Schmidt kernels of arnoldi_step. */
+ * predictor (on grids of at most 256 cells along x this is the first x-axis
+ * transform of the solve, which forms the divergence as it reads its input),
+ * the remaining axis transforms of the TPF Poisson solve (one event pair
+ * around the back-to-back launches of a solve, counted as that many
+ * launches), the velocity correction with its fused divergence check, and
+ * the Gram-Schmidt kernels of arnoldi_step. */
 enum { FVK_STAGE_JACVEC = 0, FVK_STAGE_DIV = 1, FVK_STAGE_TRANSFORM = 2, FVK_STAGE_CORRECT = 3,
        FVK_STAGE_ORTHO = 4, FVK_NSTAGES = 5 };
 /* mask: bit s enables stage s (0 = off).  Each timed stage records two

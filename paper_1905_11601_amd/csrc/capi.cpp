@@ -130,16 +130,24 @@ fvk_status simple_forward(fvk_ctx *ctx, const double *vin, double *vout, double 
     const bool want_div = sync;
     if (transposed) sync = false;
     if (p_out) launch_fill(p_out, 0.0, ctx->ncell, st);
-    timing_begin(ctx, FVK_STAGE_DIV);
-    launch_div(g, vin, w.div, st, transposed);
-    timing_end(ctx, FVK_STAGE_DIV);
+    // first right-hand side D vin: formed inside the first transform where the
+    // x axis allows it, else by the divergence kernel
+    const bool fused_div = tpf_fuses_div(ctx);
+    if (!fused_div) {
+        timing_begin(ctx, FVK_STAGE_DIV);
+        launch_div(g, vin, w.div, st, transposed);
+        timing_end(ctx, FVK_STAGE_DIV);
+    }
     const double *src = vin;
     double *dst = vout, *other = spare;
     int k = 0;
     double dmax = 0.0;
     bool scaled_out = false;
     while (true) {
-        tpf_solve(ctx, w.div, w.phi, fp32, st);
+        if (k == 0 && fused_div)
+            tpf_solve(ctx, nullptr, w.phi, fp32, st, vin, transposed ? 1 : 0);
+        else
+            tpf_solve(ctx, w.div, w.phi, fp32, st);
         const bool last_fixed = !sync && k + 1 >= fixed;
         const bool win = transposed && k == 0, wout = transposed && last_fixed;
         timing_begin(ctx, FVK_STAGE_CORRECT);

@@ -152,7 +152,12 @@ void launch_ext_T_T(const Geo &g, int span_aa, const double *src, double *dst, h
 void launch_zero_vel_walls(const Geo &g, const double *src, double *dst, hipStream_t st);
 
 // ---- TPF (kernels_tpf.hip)
-void tpf_solve(fvk_ctx *ctx, const double *b, double *phi, bool fp32, hipStream_t st);
+// phi = L^+ b by the TPF transforms.  With vel != nullptr (only where
+// tpf_fuses_div), b is not read: the right-hand side is D vel (win: D W^-1 vel)
+// formed inside the first transform.
+void tpf_solve(fvk_ctx *ctx, const double *b, double *phi, bool fp32, hipStream_t st,
+               const double *vel = nullptr, int win = 0);
+bool tpf_fuses_div(const fvk_ctx *ctx);
 
 // ---- BLAS-like kernels (kernels_blas.hip)
 int multidot_blocks(size_t n);

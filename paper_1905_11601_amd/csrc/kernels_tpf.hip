@@ -183,14 +183,22 @@ __device__ __forceinline__ double recip(double d) {
 }
 __device__ __forceinline__ float recip(float d) { return 1.0f / d; }
 
+//
+// DIV (x-axis forward only): the input is not an array of cell values but
+// the velocity fields X (3 stored fields, geometry dg); the value at cell
+// (i, j, k) is the divergence D v there (DIV = 1) or D W^-1 v (DIV = 2, the
+// transposed projection), formed from the six face values when the pencil is
+// staged -- the divergence kernel and its array are skipped.
 template <typename Tc, typename Tin, typename Tout, bool XAX, bool SCALE, bool FWD, int NW,
-          int CP>
+          int CP, int DIV = 0>
 __global__ __launch_bounds__(64 * NW) void k_axis_sym(const Tc *__restrict__ M, AxisView v,
                                                       const Tin *__restrict__ X,
                                                       Tout *__restrict__ Y,
                                                       const Tc *__restrict__ lamR,
                                                       const Tc *__restrict__ lam0,
-                                                      const Tc *__restrict__ lam1) {
+                                                      const Tc *__restrict__ lam1,
+                                                      Geo dg = Geo{}) {
+    static_assert(DIV == 0 || (XAX && FWD), "divergence input: x-axis forward transform");
     typedef SymTile<NW, CP> G;
     constexpr int KC = G::KC, TT = G::TT, TP = G::TP, LDT = G::LDT, LDP = G::LDP,
                   NTT = G::NTT;
@@ -206,6 +214,35 @@ __global__ __launch_bounds__(64 * NW) void k_axis_sym(const Tc *__restrict__ M, 
     // fetch only issues loads (raw values, clamped addresses); masking and the
     // even/odd fold happen in put, after the MFMAs of the current chunk
     Tc rme[G::NM], rmo[G::NM], rxa[G::NX], rxb[G::NX];
+    // DIV: the six face values of both mirrored cells, raw
+    constexpr int ND = DIV ? G::NX : 1;
+    double fa[ND][6], fb[ND][6];
+    // cell (i, j, k) of pencil column gp (x axis: columns = (k, j)) at x index kc
+    auto face_loads = [&](int gp, int kc, double *f) {
+        const int kz = col_hi(v, gp), jy = gp - kz * v.n0;
+        const int i = kc + 1, j = jy + 1, k = kz + 1;
+        const long p = (long(k) * dg.np[1] + j) * dg.np[0] + i;
+        f[0] = X[p];
+        f[1] = X[p - 1];
+        f[2] = X[dg.F + p];
+        f[3] = X[dg.F + p - dg.s[1]];
+        f[4] = X[2 * dg.F + p];
+        f[5] = X[2 * dg.F + p - dg.s[2]];
+    };
+    auto face_div = [&](int gp, int kc, const double *f) -> double {
+        const int kz = col_hi(v, gp), jy = gp - kz * v.n0;
+        const int i = kc + 1, j = jy + 1, k = kz + 1;
+        const double hx = dg.ax[0].ih[i], hy = dg.ax[1].ih[j], hz = dg.ax[2].ih[k];
+        if (DIV == 1) return (f[0] - f[1]) * hx + (f[2] - f[3]) * hy + (f[4] - f[5]) * hz;
+        // D W^-1 v: interior faces scaled by 1/W, wall faces 0
+        const double up = i < dg.n[0] ? f[0] * (dg.ax[0].id[i] * hy * hz) : 0.0;
+        const double um = i > 1 ? f[1] * (dg.ax[0].id[i - 1] * hy * hz) : 0.0;
+        const double vp = j < dg.n[1] ? f[2] * (dg.ax[1].id[j] * hz * hx) : 0.0;
+        const double vm = j > 1 ? f[3] * (dg.ax[1].id[j - 1] * hz * hx) : 0.0;
+        const double wp = k < dg.n[2] ? f[4] * (dg.ax[2].id[k] * hx * hy) : 0.0;
+        const double wm = k > 1 ? f[5] * (dg.ax[2].id[k - 1] * hx * hy) : 0.0;
+        return (up - um) * hx + (vp - vm) * hy + (wp - wm) * hz;
+    };
     auto fetch = [&](int c) {
         const int kb = c * KC;
 #pragma unroll
@@ -221,7 +258,11 @@ __global__ __launch_bounds__(64 * NW) void k_axis_sym(const Tc *__restrict__ M, 
             const int p = XAX ? e / KC : e % TP, kk = XAX ? e % KC : e / TP;
             const int k = kb + kk;
             const long base = col_addr(v, min(p0 + p, v.ncols - 1));
-            if (FWD) {
+            if (DIV) {
+                const int kc = min(k, n - 1), gp = min(p0 + p, v.ncols - 1);
+                face_loads(gp, kc, fa[DIV ? q : 0]);
+                face_loads(gp, n - 1 - kc, fb[DIV ? q : 0]);
+            } else if (FWD) {
                 const int kc = min(k, n - 1);
                 rxa[q] = Tc(X[base + long(kc) * v.sb]);
                 rxb[q] = Tc(X[base + long(n - 1 - kc) * v.sb]);
@@ -250,6 +291,11 @@ __global__ __launch_bounds__(64 * NW) void k_axis_sym(const Tc *__restrict__ M, 
             if (e < TP * KC) {
                 const bool in = p0 + p < v.ncols;
                 Tc a, b;
+                if (DIV) {
+                    const int kc = min(k, n - 1), gp = min(p0 + p, v.ncols - 1);
+                    rxa[q] = Tc(face_div(gp, kc, fa[DIV ? q : 0]));
+                    rxb[q] = Tc(face_div(gp, n - 1 - kc, fb[DIV ? q : 0]));
+                }
                 if (FWD) {
                     a = k < no ? rxa[q] + rxb[q] : (k < ne ? rxa[q] : Tc(0));   // middle
                     b = k < no ? rxa[q] - rxb[q] : Tc(0);
@@ -328,12 +374,45 @@ __global__ __launch_bounds__(64 * NW) void k_axis_sym(const Tc *__restrict__ M, 
         }
 }
 
-template <typename Tc, typename Tin, typename Tout, bool XAX, bool SCALE, bool FWD, int NW, int CP>
+template <typename Tc, typename Tin, typename Tout, bool XAX, bool SCALE, bool FWD, int NW, int CP,
+          int DIV = 0>
 void launch_sym(const Tc *M, const AxisView &v, const Tin *X, Tout *Y, const Tc *lR,
-                const Tc *l0, const Tc *l1, hipStream_t st) {
+                const Tc *l0, const Tc *l1, hipStream_t st, const Geo &dg = Geo{}) {
     const int nb = (v.ncols + 16 * CP - 1) / (16 * CP);
-    k_axis_sym<Tc, Tin, Tout, XAX, SCALE, FWD, NW, CP>
-        <<<nb, 64 * NW, 0, st>>>(M, v, X, Y, lR, l0, l1);
+    k_axis_sym<Tc, Tin, Tout, XAX, SCALE, FWD, NW, CP, DIV>
+        <<<nb, 64 * NW, 0, st>>>(M, v, X, Y, lR, l0, l1, dg);
+}
+
+// x-axis forward transform of the divergence of the velocity fields X (DIV as
+// in k_axis_sym); returns false when the axis is not handled this way
+template <typename Tc, int DIV>
+bool run_sym_div(const Tc *M, const AxisView &v, const double *X, Tc *Y, const Geo &dg,
+                 hipStream_t st) {
+    const int ne = v.na - v.na / 2;
+    const bool cp2 = (v.ncols + 31) / 32 >= 1024;
+    const Tc *none = nullptr;
+#define FVK_DIV_CASE(W)                                                                    \
+    case W:                                                                                \
+        if (cp2)                                                                           \
+            launch_sym<Tc, double, Tc, true, false, true, W, 2, DIV>(M, v, X, Y, none, none, \
+                                                                     none, st, dg);        \
+        else                                                                               \
+            launch_sym<Tc, double, Tc, true, false, true, W, 1, DIV>(M, v, X, Y, none, none, \
+                                                                     none, st, dg);        \
+        return true;
+    switch ((ne + 15) / 16) {
+        FVK_DIV_CASE(1)
+        FVK_DIV_CASE(2)
+        FVK_DIV_CASE(3)
+        FVK_DIV_CASE(4)
+        FVK_DIV_CASE(5)
+        FVK_DIV_CASE(6)
+        FVK_DIV_CASE(7)
+        FVK_DIV_CASE(8)
+        default:
+            return false;
+    }
+#undef FVK_DIV_CASE
 }
 
 // one wave per 16 rows of the half length ne = ceil(N/2) <= 256; two pencil
@@ -567,7 +646,7 @@ void axis_step(const AxisFactors<Tc> &f, const AxisView &v, const Tin *X, Tout *
 
 template <typename Tc>
 void tpf_typed(fvk_ctx *ctx, const double *b, double *phi, const AxisFactors<Tc> *F,
-               hipStream_t st) {
+               hipStream_t st, const double *vel, int win) {
     const int nx = ctx->n[0], ny = ctx->n[1], nz = ctx->n[2];
     const long pl = long(nx) * ny;
     // axis x: rows i, columns (k, j); axis y: rows j, columns (k, i);
@@ -578,20 +657,40 @@ void tpf_typed(fvk_ctx *ctx, const double *b, double *phi, const AxisFactors<Tc>
     Tc *t0 = static_cast<Tc *>(ctx->ws.tb0);
     Tc *t1 = static_cast<Tc *>(ctx->ws.tb1);
     const Tc *none = nullptr;
-    // one event pair around the six back-to-back launches
-    timing_begin(ctx, FVK_STAGE_TRANSFORM);
-    axis_step<Tc, double, Tc, true, false, true>(F[0], vx, b, t0, none, none, none, st);
+    // one event pair around the back-to-back transform launches; the x
+    // transform that also forms the divergence counts as the divergence stage
+    if (vel) {   // the caller checked tpf_fuses_div
+        timing_begin(ctx, FVK_STAGE_DIV);
+        if (win)
+            run_sym_div<Tc, 2>(F[0].fwd, vx, vel, t0, ctx->geo, st);
+        else
+            run_sym_div<Tc, 1>(F[0].fwd, vx, vel, t0, ctx->geo, st);
+        timing_end(ctx, FVK_STAGE_DIV);
+        timing_begin(ctx, FVK_STAGE_TRANSFORM);
+    } else {
+        timing_begin(ctx, FVK_STAGE_TRANSFORM);
+        axis_step<Tc, double, Tc, true, false, true>(F[0], vx, b, t0, none, none, none, st);
+    }
     axis_step<Tc, Tc, Tc, false, false, true>(F[1], vy, t0, t1, none, none, none, st);
     axis_step<Tc, Tc, Tc, false, true, true>(F[2], vz, t1, t0, F[2].lam, F[0].lam, F[1].lam, st);
     axis_step<Tc, Tc, Tc, false, false, false>(F[2], vz, t0, t1, none, none, none, st);
     axis_step<Tc, Tc, Tc, false, false, false>(F[1], vy, t1, t0, none, none, none, st);
     axis_step<Tc, Tc, double, true, false, false>(F[0], vx, t0, phi, none, none, none, st);
-    timing_end(ctx, FVK_STAGE_TRANSFORM, 6);
+    timing_end(ctx, FVK_STAGE_TRANSFORM, vel ? 5 : 6);
 }
 
 }  // namespace
 
-void tpf_solve(fvk_ctx *ctx, const double *b, double *phi, bool fp32, hipStream_t st) {
+bool tpf_fuses_div(const fvk_ctx *ctx) {
+    // the streaming even/odd kernel, up to 256 cells along x (for 193..256
+    // cells it replaces the register-resident transform: its six face values
+    // per cell do not fit beside the resident factors)
+    const int ne = ctx->n[0] - ctx->n[0] / 2;
+    return ctx->n[0] <= kSymMax && ne <= 128;
+}
+
+void tpf_solve(fvk_ctx *ctx, const double *b, double *phi, bool fp32, hipStream_t st,
+               const double *vel, int win) {
     const Workspace &w = ctx->ws;
     if (fp32) {
         AxisFactors<float> F[3];
@@ -600,7 +699,7 @@ void tpf_solve(fvk_ctx *ctx, const double *b, double *phi, bool fp32, hipStream_
             F[a] = {sym ? w.Ah32[a] : w.Einv32[a], sym ? w.Bh32[a] : w.E32[a],
                     sym ? w.lamp32[a] : w.lam32[a], sym};
         }
-        tpf_typed<float>(ctx, b, phi, F, st);
+        tpf_typed<float>(ctx, b, phi, F, st, vel, win);
     } else {
         AxisFactors<double> F[3];
         for (int a = 0; a < 3; ++a) {
@@ -608,7 +707,7 @@ void tpf_solve(fvk_ctx *ctx, const double *b, double *phi, bool fp32, hipStream_
             F[a] = {sym ? w.Ah[a] : w.Einv[a], sym ? w.Bh[a] : w.E[a],
                     sym ? w.lamp[a] : w.lam[a], sym};
         }
-        tpf_typed<double>(ctx, b, phi, F, st);
+        tpf_typed<double>(ctx, b, phi, F, st, vel, win);
     }
 }
 
