@@ -211,12 +211,39 @@ __global__ __launch_bounds__(BX *BY) void k_jac(Geo g, Coefs c, int span_aa,
 
 constexpr int TX = 64, TY = 4, TWP = TX + 2, THP = TY + 2, PLANE = TWP * THP, NF = 8;
 
+// The thread's own column (offset 0 in i and j) at planes k-1, k, k+1 is
+// carried in registers along the k-march: each centre value is read from LDS
+// once (when its plane is staged) instead of at every use, which halves the
+// LDS reads per point.
 struct TileAcc {
     const double *s[3];   // planes k-1, k, k+1
     int c;                // LDS offset of this thread's centre point
+    double cen[3][NF];    // centres of planes k-1, k, k+1
     template <int D0, int D1, int D2>
     __device__ __forceinline__ double at(int f) const {
+        if (D0 == 0 && D1 == 0) return cen[D2 + 1][f];
         return s[D2 + 1][f * PLANE + c + D1 * TWP + D0];
+    }
+    // before the march: centres of the first two planes (staged in pm, p0)
+    __device__ __forceinline__ void first_centres(const double *pm, const double *p0) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            cen[0][f] = pm[f * PLANE + c];
+            cen[1][f] = p0[f * PLANE + c];
+        }
+    }
+    // after the planes of a step are staged: centres of plane k+1
+    __device__ __forceinline__ void read_centres() {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) cen[2][f] = s[2][f * PLANE + c];
+    }
+    // end of a step: k+1 becomes k, k becomes k-1
+    __device__ __forceinline__ void shift() {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            cen[0][f] = cen[1][f];
+            cen[1][f] = cen[2][f];
+        }
     }
 };
 
@@ -228,6 +255,15 @@ struct TileAcc {
 #define AT2(X, f, a1, s1, a2, s2) X.template at<OFF2(a1, s1, a2, s2)>(f)
 #define AT1(X, f, a1, s1) AT2(X, f, a1, s1, a1, 0)
 
+// Grid coefficients are read-only during a kernel: reading them through the
+// constant address space marks the loads invariant, so uniform ones (the z
+// set of a k-march step) become scalar loads and loop-invariant ones are
+// hoisted -- none of them then waits behind the plane prefetch on the vector
+// memory counter.
+__device__ __forceinline__ double gc(const double *p, int i) {
+    return ((const __attribute__((address_space(4))) double *)p)[i];
+}
+
 // Grid coefficients of one axis at one index i of that axis:
 // 1/h[i], 1/h[i+1], 1/d[i], 1/d[i-1], w[i], w[i-1].  For x and y they are
 // constant along a thread's k-march and live in registers; the z set is
@@ -237,7 +273,8 @@ struct AxC {
 };
 
 __device__ __forceinline__ AxC axc(const AxisDev &a, int i) {
-    return AxC{a.ih[i], a.ih[i + 1], a.id[i], a.id[i - 1], a.w[i], a.w[i - 1]};
+    return AxC{gc(a.ih, i), gc(a.ih, i + 1), gc(a.id, i), gc(a.id, i - 1), gc(a.w, i),
+               gc(a.w, i - 1)};
 }
 
 // field indices in the accessor: perturbation u v w T = 0..3, base = 4..7
@@ -313,9 +350,10 @@ __device__ __forceinline__ void lds_barrier() {
 constexpr int NT_T = TX * TY;
 constexpr int PER_T = (PLANE + NT_T - 1) / NT_T;   // plane entries per thread per field
 
-// global -> registers for one plane (tile + halo) of all fields.  Branch-free:
-// out-of-box entries load a clamped (valid) address and are then zeroed, so
-// all NF * PER_T loads are issued back to back.
+// global -> registers for one plane (tile + halo) of all fields.  Branch-free
+// and use-free: every entry loads a clamped (valid) address, and the entries
+// outside the stored box are zeroed only in put_plane, one step later -- so
+// the NF * PER_T loads stay in flight across the whole step.
 __device__ __forceinline__ void fetch_plane(const Geo &g, const double *const *fp, int i0, int j0,
                                             int kk, int tid, double (&reg)[NF][PER_T]) {
     const long base = long(kk) * g.s[2];
@@ -323,23 +361,21 @@ __device__ __forceinline__ void fetch_plane(const Geo &g, const double *const *f
     for (int q = 0; q < PER_T; ++q) {
         const int r = min(tid + q * NT_T, PLANE - 1);
         const int gi = i0 + r % TWP, gj = j0 + r / TWP;
-        const bool ok = gi < g.np[0] && gj < g.np[1];
         const long off = base + long(min(gj, g.np[1] - 1)) * g.s[1] + min(gi, g.np[0] - 1);
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            const double v = fp[f][off];
-            reg[f][q] = ok ? v : 0.0;
-        }
+        for (int f = 0; f < NF; ++f) reg[f][q] = fp[f][off];
     }
 }
 
-__device__ __forceinline__ void put_plane(double *dst, int tid, const double (&reg)[NF][PER_T]) {
+__device__ __forceinline__ void put_plane(const Geo &g, int i0, int j0, double *dst, int tid,
+                                          const double (&reg)[NF][PER_T]) {
 #pragma unroll
     for (int q = 0; q < PER_T; ++q) {
         const int r = tid + q * NT_T;
+        const bool ok = i0 + r % TWP < g.np[0] && j0 + r / TWP < g.np[1];
         if (r < PLANE) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) dst[f * PLANE + r] = reg[f][q];
+            for (int f = 0; f < NF; ++f) dst[f * PLANE + r] = ok ? reg[f][q] : 0.0;
         }
     }
 }
@@ -402,27 +438,33 @@ __global__ __launch_bounds__(TX *TY, 2) void k_jac_tiled(Geo g, Coefs c, int spa
     C[1] = axc(g.ax[1], min(j, ny));
     double reg[NF][PER_T];
     fetch_plane(g, fp, i0, j0, kb - 1, tid, reg);
-    put_plane(lds[(kb - 1) % 3], tid, reg);
+    put_plane(g, i0, j0, lds[(kb - 1) % 3], tid, reg);
     fetch_plane(g, fp, i0, j0, kb, tid, reg);
-    put_plane(lds[kb % 3], tid, reg);
+    put_plane(g, i0, j0, lds[kb % 3], tid, reg);
     fetch_plane(g, fp, i0, j0, kb + 1, tid, reg);
     TileAcc X;
     X.c = (ty + 1) * TWP + tx + 1;
+    lds_barrier();
+    if (act) X.first_centres(lds[(kb - 1) % 3], lds[kb % 3]);
     for (int k = kb; k <= ke; ++k) {
-        put_plane(lds[(k + 1) % 3], tid, reg);
+        put_plane(g, i0, j0, lds[(k + 1) % 3], tid, reg);
         lds_barrier();
-        if (k + 2 <= ke + 1) fetch_plane(g, fp, i0, j0, k + 2, tid, reg);
+        // always issued (clamped to the last stored plane) so that the count
+        // of loads in flight after this point is the same on every step
+        fetch_plane(g, fp, i0, j0, min(k + 2, nz + 1), tid, reg);
         C[2] = axc(g.ax[2], k);
         if (act) {
             X.s[0] = lds[(k - 1) % 3];
             X.s[1] = lds[k % 3];
             X.s[2] = lds[(k + 1) % 3];
+            X.read_centres();
             const double u = (i <= nx - 1) ? jrow_mom<0>(C, X, c.nu, c.b) : 0.0;
             const double v = (j <= ny - 1) ? jrow_mom<1>(C, X, c.nu, c.b) : 0.0;
             const double w = (k <= nz - 1) ? jrow_mom<2>(C, X, c.nu, c.b) : 0.0;
             const double t = jrow_energy(C, X, c.kappa);
             store4(g, yv, yT, i, j, k, u, v, w, t);
             wall_writes(g, yv, yT, i, j, k, span_aa ? t : 0.0, span_aa ? t : 0.0);
+            X.shift();
         }
         lds_barrier();
     }
@@ -450,40 +492,50 @@ __global__ __launch_bounds__(TX *TY, 2) void k_jac_tiled(Geo g, Coefs c, int spa
 // Transposed momentum-variable output for component A at stored position
 // (i, j, k): collects every row in which x_A at this position appears, using
 // the flux-adjoint form g = (row differences of Y) of each flux.
+// Coefficients of one axis around index m, as the transposed rows use them:
+// 1/h and 1/d at m-1, m, m+1; w at m-1, m (the arrays are padded to cover
+// m = 0 and m = n+1).  The x and y sets are fixed along a thread's k-march
+// and live in registers; the z set is uniform per step (scalar loads).
+struct AxT {
+    double ihm, ih0, ihp, idm, id0, idp, wm, w0;
+};
+
+__device__ __forceinline__ AxT axt(const AxisDev &a, int m) {
+    return AxT{gc(a.ih, m - 1), gc(a.ih, m), gc(a.ih, m + 1), gc(a.id, m - 1),
+               gc(a.id, m),     gc(a.id, m + 1), gc(a.w, m - 1), gc(a.w, m)};
+}
+
 template <int A, class Acc>
-__device__ __forceinline__ double jt_vel(const Geo &g, Coefs c, const int *idx, const Acc &X) {
-    const AxisDev &aA = g.ax[A];
-    const int ia = idx[A];
+__device__ __forceinline__ double jt_vel(const AxT *T, Coefs c, const Acc &X) {
+    const AxT &TA = T[A];
     const double yc = AT1(X, A, A, 0), ym = AT1(X, A, A, -1), yp = AT1(X, A, A, 1);
     // viscous, normal direction
-    double lapT = -(aA.ih[ia + 1] + aA.ih[ia]) * aA.id[ia] * yc + aA.ih[ia] * aA.id[ia - 1] * ym +
-                  aA.ih[ia + 1] * aA.id[ia + 1] * yp;
-    // advection, normal direction: - [Ubar(c=ia) gn(ia) + Ubar(c=ia+1) gn(ia+1)]
+    double lapT = -(TA.ihp + TA.ih0) * TA.id0 * yc + TA.ih0 * TA.idm * ym + TA.ihp * TA.idp * yp;
+    // advection, normal direction: - [Ubar(cell m) gn(m) + Ubar(cell m+1) gn(m+1)]
     const double uc = AT1(X, 4 + A, A, 0), um = AT1(X, 4 + A, A, -1), up = AT1(X, 4 + A, A, 1);
-    double advT = 0.5 * (um + uc) * (ym * aA.id[ia - 1] - yc * aA.id[ia]) +
-                  0.5 * (uc + up) * (yc * aA.id[ia] - yp * aA.id[ia + 1]);
-    const double wa = aA.w[ia];
+    double advT = 0.5 * (um + uc) * (ym * TA.idm - yc * TA.id0) +
+                  0.5 * (uc + up) * (yc * TA.id0 - yp * TA.idp);
+    const double wa = TA.w0;
 #define FVK_JT_TANGENTIAL(Bt)                                                                \
     {                                                                                        \
-        const AxisDev &aB = g.ax[Bt];                                                        \
-        const int jb = idx[Bt];                                                              \
+        const AxT &TB = T[Bt];                                                               \
         const double ymB = AT1(X, A, Bt, -1), ypB = AT1(X, A, Bt, 1);                        \
-        lapT += -(aB.id[jb] + aB.id[jb - 1]) * aB.ih[jb] * yc +                              \
-                aB.id[jb - 1] * aB.ih[jb - 1] * ymB + aB.id[jb] * aB.ih[jb + 1] * ypB;        \
-        /* U_Bt interpolated along A to this A-face, at Bt-faces jb and jb-1 */              \
+        lapT += -(TB.id0 + TB.idm) * TB.ih0 * yc + TB.idm * TB.ihm * ymB +                   \
+                TB.id0 * TB.ihp * ypB;                                                       \
+        /* U_Bt interpolated along A to this A-face, at Bt-faces m and m-1 */                \
         const double ut_p = (1.0 - wa) * AT1(X, 4 + Bt, A, 0) + wa * AT1(X, 4 + Bt, A, 1);   \
         const double ut_m =                                                                  \
             (1.0 - wa) * AT1(X, 4 + Bt, Bt, -1) + wa * AT2(X, 4 + Bt, A, 1, Bt, -1);         \
         /* (3) x_A transported in the A-rows along Bt */                                     \
-        const double gt_p = yc * aB.ih[jb] - ypB * aB.ih[jb + 1];                            \
-        const double gt_m = ymB * aB.ih[jb - 1] - yc * aB.ih[jb];                            \
-        advT += ut_p * (1.0 - aB.w[jb]) * gt_p + ut_m * aB.w[jb - 1] * gt_m;                 \
+        const double gt_p = yc * TB.ih0 - ypB * TB.ihp;                                      \
+        const double gt_m = ymB * TB.ihm - yc * TB.ih0;                                      \
+        advT += ut_p * (1.0 - TB.w0) * gt_p + ut_m * TB.wm * gt_m;                           \
         /* (4) x_A transporting U_Bt in the Bt-rows along A */                               \
         const double ybc = AT1(X, Bt, A, 0), ybA = AT1(X, Bt, A, 1);                         \
         const double ybm = AT1(X, Bt, Bt, -1), ybmA = AT2(X, Bt, A, 1, Bt, -1);              \
-        const double gq_p = ybc * aA.ih[ia] - ybA * aA.ih[ia + 1];                           \
-        const double gq_m = ybm * aA.ih[ia] - ybmA * aA.ih[ia + 1];                          \
-        advT += (1.0 - aB.w[jb]) * ut_p * gq_p + aB.w[jb - 1] * ut_m * gq_m;                 \
+        const double gq_p = ybc * TA.ih0 - ybA * TA.ihp;                                     \
+        const double gq_m = ybm * TA.ih0 - ybmA * TA.ihp;                                    \
+        advT += (1.0 - TB.w0) * ut_p * gq_p + TB.wm * ut_m * gq_m;                           \
     }
     FVK_JT_TANGENTIAL((A + 1) % 3)
     FVK_JT_TANGENTIAL((A + 2) % 3)
@@ -491,35 +543,30 @@ __device__ __forceinline__ double jt_vel(const Geo &g, Coefs c, const int *idx, 
     // (5) x_A transporting Theta in the energy rows
     const double thf = (1.0 - wa) * AT1(X, 7, A, 0) + wa * AT1(X, 7, A, 1);
     const double tc = AT1(X, 3, A, 0), tp = AT1(X, 3, A, 1);
-    advT += thf * (tc * aA.ih[ia] - tp * aA.ih[ia + 1]);
+    advT += thf * (tc * TA.ih0 - tp * TA.ihp);
     return c.nu * lapT - advT;
 }
 
 template <int A, class Acc>
-__device__ __forceinline__ void jt_temp_axis(const Geo &g, const int *idx, const Acc &X,
-                                             double tc, double &lapT, double &advT) {
-    const AxisDev &aA = g.ax[A];
-    const int ia = idx[A];
+__device__ __forceinline__ void jt_temp_axis(const AxT &TA, const Acc &X, double tc, double &lapT,
+                                             double &advT) {
     const double tm = AT1(X, 3, A, -1), tp = AT1(X, 3, A, 1);
-    lapT += -(aA.id[ia] + aA.id[ia - 1]) * aA.ih[ia] * tc + aA.id[ia - 1] * aA.ih[ia - 1] * tm +
-            aA.id[ia] * aA.ih[ia + 1] * tp;
+    lapT += -(TA.id0 + TA.idm) * TA.ih0 * tc + TA.idm * TA.ihm * tm + TA.id0 * TA.ihp * tp;
     const double uq = AT1(X, 4 + A, A, 0), uqm = AT1(X, 4 + A, A, -1);
-    const double g_p = tc * aA.ih[ia] - tp * aA.ih[ia + 1];
-    const double g_m = tm * aA.ih[ia - 1] - tc * aA.ih[ia];
-    advT += uq * (1.0 - aA.w[ia]) * g_p + uqm * aA.w[ia - 1] * g_m;
+    const double g_p = tc * TA.ih0 - tp * TA.ihp;
+    const double g_m = tm * TA.ihm - tc * TA.ih0;
+    advT += uq * (1.0 - TA.w0) * g_p + uqm * TA.wm * g_m;
 }
 
 template <class Acc>
-__device__ __forceinline__ double jt_temp(const Geo &g, Coefs c, const int *idx, const Acc &X) {
+__device__ __forceinline__ double jt_temp(const AxT *T, Coefs c, const Acc &X) {
     const double tc = AT1(X, 3, 0, 0);
     double lapT = 0.0, advT = 0.0;
-    jt_temp_axis<0>(g, idx, X, tc, lapT, advT);
-    jt_temp_axis<1>(g, idx, X, tc, lapT, advT);
-    jt_temp_axis<2>(g, idx, X, tc, lapT, advT);
+    jt_temp_axis<0>(T[0], X, tc, lapT, advT);
+    jt_temp_axis<1>(T[1], X, tc, lapT, advT);
+    jt_temp_axis<2>(T[2], X, tc, lapT, advT);
     // buoyancy: the w-rows read T at the z-centres k and k+1
-    const AxisDev &az = g.ax[2];
-    const int k = idx[2];
-    const double buo = (1.0 - az.w[k]) * AT1(X, 2, 2, 0) + az.w[k - 1] * AT1(X, 2, 2, -1);
+    const double buo = (1.0 - T[2].w0) * AT1(X, 2, 2, 0) + T[2].wm * AT1(X, 2, 2, -1);
     return c.kappa * lapT - advT + c.b * buo;
 }
 
@@ -558,12 +605,11 @@ __global__ __launch_bounds__(TX *TY, 2) void k_jacT_tiled(Geo g, Coefs c, int fo
             raw[3][q] = yT[off];
 #pragma unroll
             for (int f = 4; f < NF; ++f) raw[f][q] = base[(f - 4) * F + off];
-            // neighbours for the fold, only on the two rows next to the
-            // insulated walls
-            fm[q] = 0.0;
-            fp[q] = 0.0;
-            if (fold && gj == 1) fm[q] = yT[off - g.s[1]];
-            if (fold && gj == g.n[1]) fp[q] = yT[off + g.s[1]];
+            // neighbours for the fold (used on the two rows next to the
+            // insulated walls; elsewhere a harmless reload of the same entry,
+            // which keeps the loads unconditional)
+            fm[q] = yT[off - (gj == 1 ? g.s[1] : 0)];
+            fp[q] = yT[off + (gj == g.n[1] ? g.s[1] : 0)];
         }
     };
     auto stage = [&](int kk, double *dst) {
@@ -597,20 +643,27 @@ __global__ __launch_bounds__(TX *TY, 2) void k_jacT_tiled(Geo g, Coefs c, int fo
     fetch(kb + 1);
     TileAcc X;
     X.c = (ty + 1) * TWP + tx + 1;
+    AxT T[3];
+    T[0] = axt(g.ax[0], min(i, g.np[0] - 1));
+    T[1] = axt(g.ax[1], min(j, g.np[1] - 1));
+    lds_barrier();
+    if (act) X.first_centres(lds[(kb + 2) % 3], lds[kb % 3]);
     for (int k = kb; k <= ke; ++k) {
         stage(k + 1, lds[(k + 1) % 3]);
         lds_barrier();
-        if (k + 1 < ke + 1) fetch(k + 2);
+        fetch(k + 2);   // clamped inside: the same loads in flight on every step
         if (act) {
             X.s[0] = lds[(k + 2) % 3];
             X.s[1] = lds[k % 3];
             X.s[2] = lds[(k + 1) % 3];
-            const int idx[3] = {i, j, k};
+            X.read_centres();
+            T[2] = axt(g.ax[2], k);
             const long p = pos(g, i, j, k);
-            x[p] = jt_vel<0>(g, c, idx, X);
-            x[p + F] = jt_vel<1>(g, c, idx, X);
-            x[p + 2 * F] = jt_vel<2>(g, c, idx, X);
-            x[p + 3 * F] = jt_temp(g, c, idx, X);
+            x[p] = jt_vel<0>(T, c, X);
+            x[p + F] = jt_vel<1>(T, c, X);
+            x[p + 2 * F] = jt_vel<2>(T, c, X);
+            x[p + 3 * F] = jt_temp(T, c, X);
+            X.shift();
         }
         lds_barrier();
     }
