@@ -7,14 +7,21 @@ flow, and 64 seeded unit-norm Krylov vectors in the constraint subspace; one
 step applies simple_krylov_vec (Jacobian stencil, SIMPLE pass with the TPF
 Poisson solve, temperature projection) to all 64 vectors for both spanwise
 wall variants (conducting CC and insulated AA), i.e. 128 Krylov vectors, all
-FP64.  Inputs are resident in device memory before the timed region.
+FP64.  Inputs are resident in device memory before the timed region.  The two
+wall variants are independent problems, each with its own library context;
+on grids of up to 160^3 cells, where one problem's kernels do not fill the
+GPU, each context runs on its own HIP stream so that their kernels overlap
+(--streams 1 serialises them).  The timed region is bracketed by device
+synchronisations and timed on the host clock.
 
 Prints one JSON line: value = Krylov vectors per second, a roofline entry for
-the dominant kernel (timed live with HIP events on the library's stream) and
-a CPU baseline of the oracle on a bounded sample of the same workload.
+the dominant kernel (timed live with HIP events on the library's stream, one
+context at a time so that the kernel durations are those of the kernels
+alone) and a CPU baseline of the oracle on a bounded sample of the same
+workload.
 
 Usage: python bench.py [--steps K] [--warmup W] [--n N] [--nvec M]
-       [--no-cpu-baseline] [--no-extra]
+       [--streams S] [--no-cpu-baseline] [--no-extra]
        python bench.py --copy-calibration          (a 2 GiB device copy, for
                                                     rocprofv3 --pmc scaling)
        python bench.py --ingest-pmc FETCH WRITE CFETCH CWRITE
@@ -66,16 +73,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_inputs(fvk, torch, n, nvec, bc, prec):
+def make_inputs(fvk, torch, n, nvec, bc, prec, stream):
+    """Context on `stream`, base flow and nvec projected unit inputs, all made
+    on that stream (and finished before returning)."""
     from paper_1905_11601_amd import inputs
-    ctx = fvk.Ctx(n, grid=fvk.TANH, s=1.5, span_bc=bc, Gr=1e6, Pr=0.71, prec=prec)
-    f, c, h = ctx.coords()
-    base = torch.as_tensor(inputs.synthetic_base(f, c, h, bc)).cuda()
-    X = torch.empty((nvec,) + ctx.shape4, dtype=torch.float64, device="cuda")
-    for q in range(nvec):
-        raw = torch.as_tensor(inputs.random_fields(ctx.n, 2000 + q)).cuda()
-        ctx.project(raw, out=X[q])
-        ctx.normalize(X[q])
+    with torch.cuda.stream(stream):
+        ctx = fvk.Ctx(n, grid=fvk.TANH, s=1.5, span_bc=bc, Gr=1e6, Pr=0.71, prec=prec,
+                      stream=stream)
+        f, c, h = ctx.coords()
+        base = torch.as_tensor(inputs.synthetic_base(f, c, h, bc)).cuda()
+        X = torch.empty((nvec,) + ctx.shape4, dtype=torch.float64, device="cuda")
+        for q in range(nvec):
+            raw = torch.as_tensor(inputs.random_fields(ctx.n, 2000 + q)).cuda()
+            ctx.project(raw, out=X[q])
+            ctx.normalize(X[q])
+    stream.synchronize()
     return ctx, base, X
 
 
@@ -199,8 +211,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=100)
     ap.add_argument("--nvec", type=int, default=64)
+    ap.add_argument("--streams", type=int, default=0, choices=(0, 1, 2),
+                    help="1: both wall variants on one stream; 2: one stream each; "
+                         "0 (default): 2 up to 160^3 cells, else 1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=320)
+    ap.add_argument("--cpu-sample", type=int, default=480)
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the mixed-precision, adjoint and Arnoldi-step rates")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -221,14 +236,29 @@ def main():
     import paper_1905_11601_amd as fvk
 
     n, nvec = args.n, args.nvec
-    log(f"setup {n}^3, {nvec} vectors x 2 wall variants")
-    runs = [make_inputs(fvk, torch, n, nvec, bc, fvk.FP64) for bc in (fvk.CC, fvk.AA)]
-    Ys = [torch.empty_like(X) for (_, _, X) in runs]
+    nstreams = args.streams or (2 if n <= 160 else 1)
+    log(f"setup {n}^3, {nvec} vectors x 2 wall variants on {nstreams} stream(s)")
+    if nstreams == 2:
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]   # default priority
+    else:
+        streams = [torch.cuda.current_stream()] * 2
+    runs = [make_inputs(fvk, torch, n, nvec, bc, fvk.FP64, st)
+            for bc, st in zip((fvk.CC, fvk.AA), streams)]
+    Ys = []
+    for (_, _, X), st in zip(runs, streams):
+        with torch.cuda.stream(st):
+            Ys.append(torch.empty_like(X))
+
+    def submit(q, r):
+        ctx, base, X = runs[r]
+        ctx.simple_krylov_vec(base, X[q], out=Ys[r][q])
 
     def step():
-        for (ctx, base, X), Y in zip(runs, Ys):
-            for q in range(nvec):
-                ctx.simple_krylov_vec(base, X[q], out=Y[q])
+        # the two problems' vectors interleaved, so that both streams have
+        # work queued at any time
+        for q in range(nvec):
+            for r in range(2):
+                submit(q, r)
 
     for ctx, _, _ in runs:
         ctx.simple_stats()
@@ -236,19 +266,14 @@ def main():
         step()
     torch.cuda.synchronize()
     log(f"timing {args.steps} steps")
-    stream = torch.cuda.current_stream()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record(stream)
     for _ in range(args.steps):
         step()
-    ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    ms_total = ev0.elapsed_time(ev1)
+    ms_total = wall * 1e3
     nvec_total = 2 * nvec * args.steps
-    value = nvec_total / (ms_total / 1e3)
+    value = nvec_total / wall
     max_div = 0.0
     for ctx, _, _ in runs:
         d, bad = ctx.simple_stats()
@@ -256,15 +281,16 @@ def main():
             raise SystemExit(f"{bad} Krylov vectors failed the divergence test")
         max_div = max(max_div, d)
 
-    # ---- roofline of the dominant kernel: the same steps again with HIP-event
-    # stage timing on the library's stream
-    for ctx, _, _ in runs:
-        ctx.set_timing(("jacvec", "div", "transform", "correct"))
-    for _ in range(args.steps):
-        step()
+    # ---- roofline of the dominant kernel: the same vectors again with
+    # HIP-event stage timing on each context's stream, one context at a time
+    # (no kernels of the other problem running alongside)
     stages = {}
-    for ctx, _, _ in runs:
-        for k, (ms, cnt) in ctx.timing_read().items():
+    for r, (ctx, _, _) in enumerate(runs):
+        ctx.set_timing(("jacvec", "div", "transform", "correct"))
+        for _ in range(args.steps):
+            for q in range(nvec):
+                submit(q, r)
+        for k, (ms, cnt) in ctx.timing_read().items():   # synchronises
             a = stages.setdefault(k, [0.0, 0])
             a[0] += ms
             a[1] += cnt
@@ -318,7 +344,8 @@ def main():
         "config": {"workload": f"simple_krylov_vec, {n}^3 tanh-stretched (beta 1.5) staggered FV "
                                f"cube, Pr 0.71, Gr 1e6, synthetic divergence-free base flow, "
                                f"{nvec} seeded unit Krylov vectors x (CC, AA) spanwise walls, FP64",
-                   "grid": n, "vectors_per_step": 2 * nvec, "parallelism": "single GPU",
+                   "grid": n, "vectors_per_step": 2 * nvec,
+                   "parallelism": f"single GPU, {nstreams} stream(s)",
                    "max_div_after_simple": max_div},
         "roofline": roof,
         "wall_s": wall,
@@ -345,7 +372,13 @@ def timed(torch, fn, reps):
 
 def extra_rates(fvk, torch, runs, args):
     """Mixed-precision and transposed (adjoint) Krylov-vector rates on the same
-    vectors, and the Arnoldi-step rate at Krylov dimension 40."""
+    vectors, and the Arnoldi-step rate at Krylov dimension 40: one context,
+    one stream, vectors one after the other."""
+    with torch.cuda.stream(runs[0][0].stream):
+        return _extra_rates(fvk, torch, runs, args)
+
+
+def _extra_rates(fvk, torch, runs, args):
     ctx, base, X = runs[0]
     nvec = X.shape[0]
     Y = torch.empty_like(X)
