@@ -183,9 +183,9 @@ __device__ __forceinline__ double recip(double d) {
 }
 __device__ __forceinline__ float recip(float d) { return 1.0f / d; }
 
-//
-// DIV (x-axis forward only): the input is not an array of cell values but
-// the velocity fields X (3 stored fields, geometry dg); the value at cell
+// The even/odd transform kernel (see SymTile).  DIV (x-axis forward only):
+// the input is not an array of cell values but the velocity fields X (3
+// stored fields, geometry dg); the value at cell
 // (i, j, k) is the divergence D v there (DIV = 1) or D W^-1 v (DIV = 2, the
 // transposed projection), formed from the six face values when the pencil is
 // staged -- the divergence kernel and its array are skipped.
