@@ -101,9 +101,12 @@ def critical_gr(ctx, base, Gr0, v0, seed, k=4, m=40, tol=1e-10, gr_rtol=1e-7, ma
     Gr <- Gr - Re lambda / Re(d lambda / d Gr).  Returns a history list."""
     hist = []
     Gr = Gr0
+    prev = Gr0
     for it in range(max_it):
         if it > 0:
-            steady_state(ctx, base, Gr, Gr_start=Gr, factor=1.0, log=log)
+            # from the steady state at the previous Gr, in steps of at most 1.5x
+            steady_state(ctx, base, Gr, Gr_start=prev, factor=1.5, log=log)
+            prev = Gr
         ctx.set_params(Gr)
         r = krylov_schur(ctx, base, k, m, v0, tol=tol)
         lead = 0

@@ -172,3 +172,40 @@ def test_mixed_precision_eigenvalues(fvk):
     err = _match(r32.lam, r64.lam, 6)
     print("mixed vs fp64 eigenvalue rel error", err, flush=True)
     assert err < 1e-6
+
+
+def test_critical_grashof_6cube(fvk):
+    """Newton iteration on Gr for Re lambda = 0 (critical_gr: steady state,
+    leading right and left eigenpairs, base-flow sensitivity U' = dU/dGr, total
+    d lambda / d Gr along the branch) on the 6^3 uniform grid with conducting
+    walls, against the oracle's crossing (a secant iteration on the dense-pencil
+    eigenvalues of the oracle's own steady states) and the oracle's central
+    difference of lambda along the branch, stored by
+    tests/golden/make_critical6.py."""
+    import json
+    import os
+    from paper_1905_11601_amd.drivers import critical_gr, steady_state
+    print("case critical Gr 6^3", flush=True)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "critical_6cube.json")))
+    Gr0 = gold["Gr0"]
+    g, orc, ctx = setup((6, 6, 6), UNIFORM, 0.0, 0, Gr=1e3)
+    Ug = dev(torch.as_tensor(inputs.conduction_state(tuple(a.c for a in g.ax), 0)))
+    stages = steady_state(ctx, Ug, Gr0, Gr_start=1e3)
+    assert stages[-1][0] == Gr0 and stages[-1][1]["status"] == 0
+    v0 = dev(krylov_input(g, orc, 5000))
+    seed = dev(torch.as_tensor(inputs.random_fields(g.n, 5001)))
+    hist = critical_gr(ctx, Ug, Gr0, v0, seed, k=4, m=40, tol=1e-12, gr_rtol=1e-10,
+                       log=lambda m: print(m, flush=True))
+    assert hist[-1].get("converged")
+    lam0 = complex(*gold["lambda0"])
+    dl = complex(*gold["dlam_dGr_total_central_difference"])
+    assert abs(hist[0]["lam"] - lam0) < 1e-8 * abs(lam0)
+    assert abs(hist[0]["dlam_dGr"] - dl) < 1e-5 * abs(dl)
+    Grc = hist[-1]["Gr"]
+    assert abs(Grc - gold["Gr_critical"]) < 1e-7 * gold["Gr_critical"]
+    # the eigenvalue at the last evaluated Gr: on the imaginary axis, with the
+    # oracle's frequency
+    lam_c = hist[-2]["lam"]
+    assert abs(lam_c.real) < 1e-8
+    assert abs(lam_c.imag - gold["lambda_critical"][1]) < 1e-7
