@@ -409,6 +409,19 @@ def _extra_rates(fvk, torch, runs, args):
         ctx.arnoldi_step(base, V, j)
     torch.cuda.synchronize()
     res["arnoldi_steps_per_s_m40"] = m / (time.perf_counter() - t0)
+    # the same m steps with the lagged re-orthogonalisation (two passes over
+    # the basis per step), completed by arnoldi_finish
+    import numpy as np
+    V.zero_()
+    V[0] = X[0].reshape(-1)
+    H = np.zeros((m + 1, m))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(m):
+        ctx.arnoldi_step_lagged(base, V, j, H)
+    ctx.arnoldi_finish(V, m, H)
+    torch.cuda.synchronize()
+    res["arnoldi_lagged_steps_per_s_m40"] = m / (time.perf_counter() - t0)
     return res
 
 

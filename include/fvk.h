@@ -146,6 +146,29 @@ fvk_status fvk_simple_stats(fvk_ctx *ctx, double *max_div, int *n_unconverged);
 fvk_status arnoldi_step(fvk_ctx *ctx, const double *base, double *V, size_t ldv, int j,
                         double *h_col, int transpose);
 
+/* The same Arnoldi process (Sec. 3.1's Arnoldi iteration for the rightmost
+ * eigenvalues of eq. (10)) with the re-orthogonalisation lagged by one step,
+ * so that each step reads the basis twice instead of four times: one pass of
+ * dot products against v_j and w, one pass of updates.
+ * State between calls: V holds v_0..v_{j-1} (orthonormal) and, in slot j, a
+ * vector that is orthogonal to them only to first order and not normalised;
+ * row j of H refers to that raw vector.  Step j computes w = A (slot j)
+ * normalised, re-orthogonalises slot j (it becomes v_j), corrects the earlier
+ * columns of H for it, projects w against v_0..v_j (coefficients from the same
+ * dot products) and stores the result, un-normalised, in slot j+1; column j of
+ * H is written with H[j+1][j] = 1 (it refers to the raw slot j+1).
+ * H: host, row-major, leading dimension ldh (columns, >= j+1), at least j+2
+ * rows; rows 0..j and columns 0..j are read and written.  For j = 0 slot 0
+ * holds the start vector (any norm) and row 0 of H is empty.  Returns
+ * FVK_EBREAKDOWN if slot j is zero or lies in the span of v_0..v_{j-1}. */
+fvk_status arnoldi_step_lagged(fvk_ctx *ctx, const double *base, double *V, size_t ldv, int j,
+                               double *H, int ldh, int transpose);
+/* Completes a lagged Arnoldi sequence after step j-1: re-orthogonalises and
+ * normalises slot j into v_j and corrects row j and the columns of H above it
+ * (H as in arnoldi_step_lagged, columns 0..j-1).  Returns FVK_EBREAKDOWN as
+ * above. */
+fvk_status arnoldi_finish(fvk_ctx *ctx, double *V, size_t ldv, int j, double *H, int ldh);
+
 /* ---------------------------------------------------------------- tracing */
 
 /* Stages of the Krylov-vector path timed with HIP events on the context's

@@ -190,6 +190,32 @@ class Ctx:
             self._check(st)
         return h, st == 5
 
+    def _hess(self, H):
+        if not (isinstance(H, np.ndarray) and H.dtype == np.float64 and H.ndim == 2
+                and H.flags.c_contiguous):
+            raise ValueError("H must be a C-contiguous float64 (rows, cols) array")
+        return H.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+    def arnoldi_step_lagged(self, base, V, j, H, transpose=False):
+        """Lagged-CGS2 Arnoldi step j (see include/fvk.h): V (m+1, N) CUDA
+        tensor, H host (rows >= j+2, cols >= j+1) updated in place."""
+        if V.dim() != 2 or V.shape[1] != self.N or not V.is_contiguous() or j + 1 >= V.shape[0]:
+            raise ValueError("V must be a contiguous (m+1, N) tensor with room for vector j+1")
+        if H.shape[0] < j + 2 or H.shape[1] < j + 1:
+            raise ValueError("H too small for step j")
+        self._check(self.lib.arnoldi_step_lagged(self.h, self._vec(base, "base"), _ptr(V),
+                                                 V.shape[1], j, self._hess(H), H.shape[1],
+                                                 int(bool(transpose))))
+
+    def arnoldi_finish(self, V, j, H):
+        """Completes a lagged sequence: slot j becomes the unit vector v_j."""
+        if V.dim() != 2 or V.shape[1] != self.N or not V.is_contiguous() or j >= V.shape[0]:
+            raise ValueError("V must be a contiguous (m+1, N) tensor with a slot j")
+        if H.shape[0] < j + 1 or (j > 0 and H.shape[1] < j):
+            raise ValueError("H too small")
+        self._check(self.lib.arnoldi_finish(self.h, _ptr(V), V.shape[1], j, self._hess(H),
+                                            max(H.shape[1], 1)))
+
     def multidot(self, V, m, w):
         out = np.zeros(m)
         self._check(self.lib.fvk_multidot(self.h, _ptr(V), V.shape[-1], m, _ptr(w), self.N,

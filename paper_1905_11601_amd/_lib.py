@@ -51,6 +51,9 @@ SIGNATURES = {
                                   P(c_int), P(c_double)]),
     "fvk_simple_stats": (c_int, [c_void_p, P(c_double), P(c_int)]),
     "arnoldi_step": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_int, P(c_double), c_int]),
+    "arnoldi_step_lagged": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_int, P(c_double),
+                                    c_int, c_int]),
+    "arnoldi_finish": (c_int, [c_void_p, c_void_p, c_size_t, c_int, P(c_double), c_int]),
     "fvk_set_timing": (c_int, [c_void_p, c_int]),
     "fvk_timing_read": (c_int, [c_void_p, P(c_double), P(c_int)]),
     "fvk_multidot": (c_int, [c_void_p, c_void_p, c_size_t, c_int, c_void_p, c_size_t,

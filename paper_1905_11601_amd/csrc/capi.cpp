@@ -671,3 +671,139 @@ fvk_status arnoldi_step(fvk_ctx *ctx, const double *base, double *V, size_t ldv,
 }
 
 }  // extern "C"
+
+// ---- lagged CGS2 ------------------------------------------------------------
+// Slot j holds x (raw), orthogonal to v_0..v_{j-1} to first order; row j of
+// H refers to x.  With d_q = v_q . x (q < j), alpha = x . x:
+//   rho = |x|, s = d / rho, nu = sqrt(1 - |s|^2), v_j = (x / rho - V s) / nu,
+// and x = rho (V s + nu v_j) moves rho s * (row j) into the rows above and
+// scales row j by rho nu.  Returns the step's quantities for the caller.
+namespace {
+
+struct LagState {
+    double rho, nu;
+    std::vector<double> s;
+};
+
+fvk_status lag_finalise(fvk_ctx *ctx, int j, double *H, int ldh, const double *d_xv,
+                        double alpha, LagState &L) {
+    if (!(alpha > 0.0) || !std::isfinite(alpha))
+        return fail(ctx, FVK_EBREAKDOWN, "Arnoldi breakdown: the new vector vanished");
+    L.rho = std::sqrt(alpha);
+    L.s.assign(j, 0.0);
+    double ss = 0.0;
+    for (int q = 0; q < j; ++q) {
+        L.s[q] = d_xv[q] / L.rho;
+        ss += L.s[q] * L.s[q];
+    }
+    const double nu2 = 1.0 - ss;
+    if (!(nu2 > 1e-28))
+        return fail(ctx, FVK_EBREAKDOWN, "Arnoldi breakdown: invariant subspace");
+    L.nu = std::sqrt(nu2);
+    for (int c = 0; c < j; ++c) {
+        const double hjc = H[size_t(j) * ldh + c];
+        if (hjc == 0.0) continue;
+        for (int r = 0; r < j; ++r) H[size_t(r) * ldh + c] += L.rho * L.s[r] * hjc;
+        H[size_t(j) * ldh + c] = hjc * L.rho * L.nu;
+    }
+    return FVK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fvk_status arnoldi_step_lagged(fvk_ctx *ctx, const double *base, double *V, size_t ldv, int j,
+                               double *H, int ldh, int transpose) {
+    if (!ctx || !base || !V || !H || j < 0 || ldh < j + 1) return FVK_EINVAL;
+    const size_t n = nvec(ctx);
+    if (ldv < n) return fail(ctx, FVK_EINVAL, "ldv smaller than the vector length");
+    const int m2 = j + 2;   // rows v_0..v_{j-1}, slot j, slot j+1
+    const int nb = multidot_blocks(n);
+    if (size_t(nb) * 2 * m2 > ctx->ws.red_len || 2 * m2 + 8 > 4096 || 2 * j > int(ctx->ws.coef_len))
+        return fail(ctx, FVK_EINVAL, "Krylov dimension too large");
+    double *x = V + size_t(j) * ldv, *w = V + size_t(j + 1) * ldv;
+    fvk_status s = simple_krylov_vec(ctx, base, x, w, nullptr, transpose, nullptr, nullptr);
+    if (s != FVK_OK) return s;
+    hipStream_t st = ctx->stream;
+    double *dots = ctx->ws.dev_scalars + 8;
+    timing_begin(ctx, FVK_STAGE_ORTHO);
+    launch_multidot2(V, ldv, m2, x, w, n, ctx->ws.red, nb, st);
+    launch_reduce_partials(ctx->ws.red, nb, 2 * m2, dots, 0, st);
+    timing_end(ctx, FVK_STAGE_ORTHO);
+    CHECK_LAUNCH(ctx);
+    std::vector<double> d(2 * m2);
+    if ((s = read_back(ctx, dots, d.data(), d.size())) != FVK_OK) return s;
+    // d[2q] = v_q . x, d[2q + 1] = v_q . (A x); q = j: x itself
+    std::vector<double> dx(j), dt(j);
+    for (int q = 0; q < j; ++q) {
+        dx[q] = d[2 * q];
+        dt[q] = d[2 * q + 1];
+    }
+    LagState L;
+    if ((s = lag_finalise(ctx, j, H, ldh, dx.data(), d[2 * j], L)) != FVK_OK) return s;
+    const double rho = L.rho, nu = L.nu;
+    // A applied to the unit vector x/rho: t = V^T (A x) / rho, beta = (x . A x) / rho^2
+    std::vector<double> t(j);
+    double st_ = 0.0;
+    for (int q = 0; q < j; ++q) {
+        t[q] = dt[q] / rho;
+        st_ += L.s[q] * t[q];
+    }
+    const double beta = d[2 * j + 1] / (rho * rho);
+    // A V_j s = V_{j+1} g with the corrected columns 0..j-1
+    std::vector<double> g(j + 1, 0.0), h(j + 1), u(j + 1);
+    for (int r = 0; r <= j; ++r)
+        for (int c = 0; c < j; ++c) g[r] += H[size_t(r) * ldh + c] * L.s[c];
+    for (int r = 0; r < j; ++r) h[r] = (t[r] - g[r]) / nu;
+    h[j] = ((beta - st_) / nu - g[j]) / nu;
+    for (int r = 0; r <= j; ++r) {
+        H[size_t(r) * ldh + j] = h[r];
+        u[r] = g[r] / nu + h[r];
+    }
+    H[size_t(j + 1) * ldh + j] = 1.0;
+    // v_j = x / (rho nu) - V s / nu;
+    // w' = A x / (rho nu) - u_j x / (rho nu) - V (u - s u_j / nu)
+    std::vector<double> coef(2 * j);
+    for (int q = 0; q < j; ++q) {
+        coef[q] = -L.s[q] / nu;
+        coef[j + q] = -(u[q] - L.s[q] * u[j] / nu);
+    }
+    if (j > 0 && (s = write_coefs(ctx, coef.data(), coef.size())) != FVK_OK) return s;
+    const double c1 = 1.0 / (rho * nu);
+    timing_begin(ctx, FVK_STAGE_ORTHO);
+    launch_update2(x, w, V, ldv, j, ctx->ws.coef_dev, ctx->ws.coef_dev + j, c1, c1, -u[j] * c1, n,
+                   st);
+    timing_end(ctx, FVK_STAGE_ORTHO);
+    CHECK_LAUNCH(ctx);
+    return FVK_OK;
+}
+
+fvk_status arnoldi_finish(fvk_ctx *ctx, double *V, size_t ldv, int j, double *H, int ldh) {
+    if (!ctx || !V || !H || j < 0 || (j > 0 && ldh < j)) return FVK_EINVAL;
+    const size_t n = nvec(ctx);
+    if (ldv < n) return fail(ctx, FVK_EINVAL, "ldv smaller than the vector length");
+    const int m = j + 1;
+    const int nb = multidot_blocks(n);
+    if (size_t(nb) * m > ctx->ws.red_len || m + 8 > 4096 || j > int(ctx->ws.coef_len))
+        return fail(ctx, FVK_EINVAL, "Krylov dimension too large");
+    double *x = V + size_t(j) * ldv;
+    hipStream_t st = ctx->stream;
+    double *dots = ctx->ws.dev_scalars + 8;
+    launch_multidot(V, ldv, m, x, n, ctx->ws.red, nb, st);
+    launch_reduce_partials(ctx->ws.red, nb, m, dots, 0, st);
+    CHECK_LAUNCH(ctx);
+    std::vector<double> d(m);
+    fvk_status s = read_back(ctx, dots, d.data(), m);
+    if (s != FVK_OK) return s;
+    LagState L;
+    if ((s = lag_finalise(ctx, j, H, ldh, d.data(), d[j], L)) != FVK_OK) return s;
+    std::vector<double> coef(j);
+    for (int q = 0; q < j; ++q) coef[q] = -L.s[q] / L.nu;
+    if (j > 0 && (s = write_coefs(ctx, coef.data(), coef.size())) != FVK_OK) return s;
+    launch_multiaxpy(x, 1.0 / (L.rho * L.nu), 1.0, V, ldv, j, ctx->ws.coef_dev, n, st);
+    CHECK_LAUNCH(ctx);
+    return FVK_OK;
+}
+
+}  // extern "C"

@@ -50,6 +50,71 @@ __global__ __launch_bounds__(NT) void k_multidot(const double *__restrict__ V, s
     }
 }
 
+// Dot products of m rows of V with two vectors x and y in one pass over V:
+// partials[blk * 2m + 2q + r] = sum over this block's rows of V_q[i] * (r ? y : x)[i].
+constexpr int GROUP2 = 16;
+__global__ __launch_bounds__(NT) void k_multidot2(const double *__restrict__ V, size_t ldv, int m,
+                                                  const double *__restrict__ x,
+                                                  const double *__restrict__ y, size_t n,
+                                                  size_t chunk, double *__restrict__ partials) {
+    __shared__ double sh[2 * GROUP2][NT / 64];
+    const size_t r0 = size_t(blockIdx.x) * chunk;
+    const size_t r1 = min(n, r0 + chunk);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int q0 = 0; q0 < m; q0 += GROUP2) {
+        double ax[GROUP2], ay[GROUP2];
+#pragma unroll
+        for (int t = 0; t < GROUP2; ++t) ax[t] = ay[t] = 0.0;
+        for (size_t r = r0 + threadIdx.x; r < r1; r += NT) {
+            const double xr = x[r], yr = y[r];
+#pragma unroll
+            for (int t = 0; t < GROUP2; ++t)
+                if (q0 + t < m) {
+                    const double v = V[size_t(q0 + t) * ldv + r];
+                    ax[t] += v * xr;
+                    ay[t] += v * yr;
+                }
+        }
+#pragma unroll
+        for (int t = 0; t < GROUP2; ++t) {
+            const double sx = wave_sum(ax[t]), sy = wave_sum(ay[t]);
+            if (lane == 0) {
+                sh[2 * t][wv] = sx;
+                sh[2 * t + 1][wv] = sy;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 2 * GROUP2 && q0 + threadIdx.x / 2 < m) {
+            double s = 0.0;
+            for (int q = 0; q < NT / 64; ++q) s += sh[threadIdx.x][q];
+            partials[size_t(blockIdx.x) * 2 * m + 2 * q0 + threadIdx.x] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// The two updates of the lagged CGS2 step in one pass over V_0..V_{m-1}:
+// x <- c1 x + sum_q a[q] V_q and y <- c2 y + c3 x_old + sum_q b[q] V_q
+// (a, b on the device; x, y distinct from the V_q).
+__global__ __launch_bounds__(NT) void k_update2(double *__restrict__ x, double *__restrict__ y,
+                                                const double *__restrict__ V, size_t ldv, int m,
+                                                const double *__restrict__ a,
+                                                const double *__restrict__ b, double c1,
+                                                double c2, double c3, size_t n) {
+    const size_t r = size_t(blockIdx.x) * NT + threadIdx.x;
+    if (r >= n) return;
+    double sa = 0.0, sb = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < m; ++q) {
+        const double v = V[size_t(q) * ldv + r];
+        sa += a[q] * v;
+        sb += b[q] * v;
+    }
+    const double xo = x[r];
+    x[r] = c1 * xo + sa;
+    y[r] = c2 * y[r] + c3 * xo + sb;
+}
+
 // out[q] = (accumulate ? out[q] : 0) + sum_blk partials[blk * m + q]
 __global__ void k_reduce_partials(const double *__restrict__ partials, int nblk, int m,
                                   double *__restrict__ out, int accumulate) {
@@ -194,6 +259,18 @@ void launch_multidot(const double *V, size_t ldv, int m, const double *w, size_t
                      double *partials, int nblk, hipStream_t st) {
     const size_t chunk = (n + nblk - 1) / nblk;
     k_multidot<<<nblk, NT, 0, st>>>(V, ldv, m, w, n, chunk, partials);
+}
+
+void launch_multidot2(const double *V, size_t ldv, int m, const double *x, const double *y,
+                      size_t n, double *partials, int nblk, hipStream_t st) {
+    const size_t chunk = (n + nblk - 1) / nblk;
+    k_multidot2<<<nblk, NT, 0, st>>>(V, ldv, m, x, y, n, chunk, partials);
+}
+
+void launch_update2(double *x, double *y, const double *V, size_t ldv, int m, const double *a_dev,
+                    const double *b_dev, double c1, double c2, double c3, size_t n,
+                    hipStream_t st) {
+    k_update2<<<nblk1(n), NT, 0, st>>>(x, y, V, ldv, m, a_dev, b_dev, c1, c2, c3, n);
 }
 
 void launch_reduce_partials(const double *partials, int nblk, int m, double *out, int accumulate,

@@ -44,8 +44,13 @@ class EigResult:
 
 
 def krylov_schur(ctx, base, k, m, v0, tol=1e-10, max_restarts=200, transpose=False,
-                 vectors=True, log=None, null_tol=1e-9):
+                 vectors=True, log=None, null_tol=1e-9, lagged=True):
     """k rightmost eigenvalues (largest real part) of A (transpose: A^T).
+
+    lagged: Arnoldi steps with the re-orthogonalisation lagged by one step
+    (arnoldi_step_lagged, two passes over the basis per step, completed by
+    arnoldi_finish at the end of each cycle); False: arnoldi_step (CGS2, four
+    passes).
 
     v0: (N,) or ctx.shape4 float64 CUDA tensor (start vector; for A it should
     lie in the constraint subspace, e.g. the output of ctx.project).
@@ -65,11 +70,16 @@ def krylov_schur(ctx, base, k, m, v0, tol=1e-10, max_restarts=200, transpose=Fal
     kept = min(m - 1, max(k + 2, (m + k) // 2))
     for restart in range(max_restarts + 1):
         for j in range(p, m):
-            h, brk = ctx.arnoldi_step(base, V, j, transpose=transpose)
+            if lagged:
+                ctx.arnoldi_step_lagged(base, V, j, H, transpose=transpose)
+            else:
+                h, brk = ctx.arnoldi_step(base, V, j, transpose=transpose)
+                H[:j + 2, j] = h
+                if brk:
+                    raise RuntimeError("Arnoldi breakdown (invariant subspace)")
             nvec += 1
-            H[:j + 2, j] = h
-            if brk:
-                raise RuntimeError("Arnoldi breakdown (invariant subspace)")
+        if lagged:
+            ctx.arnoldi_finish(V, m, H)
         Hm = H[:m, :m]
         b = H[m, :m].copy()
         # residuals of the k wanted Ritz pairs: |b^T x| for unit eigenvectors x

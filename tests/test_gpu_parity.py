@@ -141,3 +141,39 @@ def test_arnoldi_step(fvk, bc):
         assert rel_err(V[j + 1], torch.as_tensor(Vo[j + 1])) < 1e-9
     G = (V @ V.T).cpu().numpy()
     assert np.max(np.abs(G - np.eye(4))) < 1e-13
+
+
+@pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
+@pytest.mark.parametrize("transpose", [False, True], ids=["A", "AT"])
+def test_arnoldi_step_lagged(fvk, bc, transpose):
+    """The lagged re-orthogonalisation (two passes over the basis per step)
+    gives the Arnoldi basis and Hessenberg matrix of classical Gram-Schmidt
+    with full re-orthogonalisation, computed here in NumPy on the oracle's
+    Krylov vectors, once the sequence is completed by arnoldi_finish."""
+    print(f"case arnoldi lagged bc={bc} transpose={transpose}", flush=True)
+    g, orc, ctx = setup((10, 9, 11), TANH, 1.5, bc)
+    U = base(g, bc)
+    m = 6
+    x0 = krylov_input(g, orc, 5000)
+    V = torch.zeros(m + 1, ctx.N, dtype=torch.float64, device="cuda")
+    V[0] = dev(x0).reshape(-1)
+    H = np.zeros((m + 1, m))
+    for j in range(m):
+        ctx.arnoldi_step_lagged(dev(U), V, j, H, transpose=transpose)
+    ctx.arnoldi_finish(V, m, H)
+    op = orc.krylov_vec_T if transpose else orc.krylov_vec
+    Vo = [x0.reshape(-1).numpy()]
+    Ho = np.zeros((m + 1, m))
+    for j in range(m):
+        w = op(U, torch.as_tensor(Vo[j].reshape(orc.shape4))).reshape(-1).numpy()
+        for _ in range(2):
+            c = np.array([Vo[q] @ w for q in range(j + 1)])
+            w = w - sum(c[q] * Vo[q] for q in range(j + 1))
+            Ho[:j + 1, j] += c
+        Ho[j + 1, j] = np.linalg.norm(w)
+        Vo.append(w / Ho[j + 1, j])
+    assert np.max(np.abs(H - Ho)) < 1e-10 * np.abs(Ho).max()
+    for j in range(m + 1):
+        assert rel_err(V[j], torch.as_tensor(Vo[j])) < 1e-9
+    G = (V @ V.T).cpu().numpy()
+    assert np.max(np.abs(G - np.eye(m + 1))) < 1e-13

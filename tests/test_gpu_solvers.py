@@ -23,14 +23,15 @@ def _match(lam, ref, k):
 
 
 @pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
-def test_krylov_schur_matches_dense_pencil(fvk, bc):
+@pytest.mark.parametrize("lagged", [True, False], ids=["lagged", "cgs2"])
+def test_krylov_schur_matches_dense_pencil(fvk, bc, lagged):
     from paper_1905_11601_amd.eigs import krylov_schur, ritz_residual
-    print(f"case eigs 5^3 bc={bc}", flush=True)
+    print(f"case eigs 5^3 bc={bc} lagged={lagged}", flush=True)
     g, orc, ctx = setup((5, 5, 5), TANH, 1.5, bc)
     U = base(g, bc)
     lam_p = dense_pencil_eigs(g, orc.prm, U, bc)
     v0 = dev(krylov_input(g, orc, 5000))
-    r = krylov_schur(ctx, dev(U), k=6, m=30, v0=v0, tol=1e-11)
+    r = krylov_schur(ctx, dev(U), k=6, m=30, v0=v0, tol=1e-11, lagged=lagged)
     assert r.converged
     assert _match(r.lam, lam_p[:10], 6) < 1e-9
     for q in range(len(r.lam)):
