@@ -160,7 +160,9 @@ fvk_status arnoldi_step(fvk_ctx *ctx, const double *base, double *V, size_t ldv,
  * H: host, row-major, leading dimension ldh (columns, >= j+1), at least j+2
  * rows; rows 0..j and columns 0..j are read and written.  For j = 0 slot 0
  * holds the start vector (any norm) and row 0 of H is empty.  Returns
- * FVK_EBREAKDOWN if slot j is zero or lies in the span of v_0..v_{j-1}. */
+ * FVK_EBREAKDOWN if slot j is zero or lies in the span of v_0..v_{j-1} (the
+ * Krylov space is invariant): then H is corrected with row j set to zero and
+ * V is left as it was. */
 fvk_status arnoldi_step_lagged(fvk_ctx *ctx, const double *base, double *V, size_t ldv, int j,
                                double *H, int ldh, int transpose);
 /* Completes a lagged Arnoldi sequence after step j-1: re-orthogonalises and

@@ -685,27 +685,29 @@ struct LagState {
     std::vector<double> s;
 };
 
+// On a breakdown (x = 0, or x in the span of v_0..v_{j-1}) H is still
+// corrected, with a zero row j: the Krylov space is invariant.
 fvk_status lag_finalise(fvk_ctx *ctx, int j, double *H, int ldh, const double *d_xv,
                         double alpha, LagState &L) {
-    if (!(alpha > 0.0) || !std::isfinite(alpha))
-        return fail(ctx, FVK_EBREAKDOWN, "Arnoldi breakdown: the new vector vanished");
-    L.rho = std::sqrt(alpha);
+    const bool vanished = !(alpha > 0.0) || !std::isfinite(alpha);
+    L.rho = vanished ? 0.0 : std::sqrt(alpha);
     L.s.assign(j, 0.0);
     double ss = 0.0;
-    for (int q = 0; q < j; ++q) {
+    for (int q = 0; q < j && !vanished; ++q) {
         L.s[q] = d_xv[q] / L.rho;
         ss += L.s[q] * L.s[q];
     }
     const double nu2 = 1.0 - ss;
-    if (!(nu2 > 1e-28))
-        return fail(ctx, FVK_EBREAKDOWN, "Arnoldi breakdown: invariant subspace");
-    L.nu = std::sqrt(nu2);
+    const bool in_span = !vanished && !(nu2 > 1e-28);
+    L.nu = (vanished || in_span) ? 0.0 : std::sqrt(nu2);
     for (int c = 0; c < j; ++c) {
         const double hjc = H[size_t(j) * ldh + c];
         if (hjc == 0.0) continue;
         for (int r = 0; r < j; ++r) H[size_t(r) * ldh + c] += L.rho * L.s[r] * hjc;
         H[size_t(j) * ldh + c] = hjc * L.rho * L.nu;
     }
+    if (vanished) return fail(ctx, FVK_EBREAKDOWN, "Arnoldi breakdown: the new vector vanished");
+    if (in_span) return fail(ctx, FVK_EBREAKDOWN, "Arnoldi breakdown: invariant subspace");
     return FVK_OK;
 }
 

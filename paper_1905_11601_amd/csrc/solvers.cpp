@@ -95,33 +95,49 @@ fvk_status gmres(Dev &d, const double *base, const double *b, double *x, double 
     d.axpby(r, -1.0, tmp, 1.0);
     double beta = d.nrm(r);
     if (d.st != FVK_OK) return d.st;
-    std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), gvec(m + 1), hcol(m + 2), y(m);
+    std::vector<double> H(size_t(m + 1) * m), Ha(size_t(m + 1) * m), cs(m), sn(m), gvec(m + 1),
+        hcol(m + 2), y(m);
     *cycles = 0;
     while (beta / bn > tol && *cycles < max_cycles) {
         d.copy(V, r);
         launch_scale(V, 1.0 / beta, n, ctx->stream);
         std::fill(gvec.begin(), gvec.end(), 0.0);
+        std::fill(Ha.begin(), Ha.end(), 0.0);
         gvec[0] = beta;
         int jend = 0;
-        for (int j = 0; j < m; ++j) {
-            fvk_status s = arnoldi_step(ctx, base, V, n, j, hcol.data(), 0);
-            ++*nvec;
-            if (s != FVK_OK && s != FVK_EBREAKDOWN) return s;
-            for (int i = 0; i < j; ++i) {   // previous rotations
+        // Column c of the Arnoldi matrix Ha is final once step c+1 (or the
+        // closing arnoldi_finish) has re-orthogonalised v_{c+1}; the Givens
+        // rotations and the residual estimate follow one step behind.
+        auto column = [&](int c) {
+            for (int i = 0; i <= c + 1; ++i) hcol[i] = Ha[size_t(i) * m + c];
+            for (int i = 0; i < c; ++i) {   // previous rotations
                 const double t = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
                 hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
                 hcol[i] = t;
             }
-            const double hh = std::hypot(hcol[j], hcol[j + 1]);
-            cs[j] = hh > 0 ? hcol[j] / hh : 1.0;
-            sn[j] = hh > 0 ? hcol[j + 1] / hh : 0.0;
-            hcol[j] = hh;
-            hcol[j + 1] = 0.0;
-            gvec[j + 1] = -sn[j] * gvec[j];
-            gvec[j] = cs[j] * gvec[j];
-            for (int i = 0; i <= j; ++i) H[size_t(i) * m + j] = hcol[i];
-            jend = j + 1;
-            if (std::fabs(gvec[j + 1]) / bn <= tol || s == FVK_EBREAKDOWN) break;
+            const double hh = std::hypot(hcol[c], hcol[c + 1]);
+            cs[c] = hh > 0 ? hcol[c] / hh : 1.0;
+            sn[c] = hh > 0 ? hcol[c + 1] / hh : 0.0;
+            hcol[c] = hh;
+            hcol[c + 1] = 0.0;
+            gvec[c + 1] = -sn[c] * gvec[c];
+            gvec[c] = cs[c] * gvec[c];
+            for (int i = 0; i <= c; ++i) H[size_t(i) * m + c] = hcol[i];
+            jend = c + 1;
+            return std::fabs(gvec[c + 1]) / bn <= tol;
+        };
+        bool done = false;
+        for (int j = 0; j < m && !done; ++j) {
+            fvk_status s = arnoldi_step_lagged(ctx, base, V, n, j, Ha.data(), m, 0);
+            if (s != FVK_OK && s != FVK_EBREAKDOWN) return s;
+            ++*nvec;
+            if (j > 0) done = column(j - 1) || s == FVK_EBREAKDOWN;
+            else if (s == FVK_EBREAKDOWN) return s;   // the start vector vanished
+        }
+        if (!done) {
+            const fvk_status s = arnoldi_finish(ctx, V, n, m, Ha.data(), m);
+            if (s != FVK_OK && s != FVK_EBREAKDOWN) return s;
+            column(m - 1);
         }
         for (int i = jend - 1; i >= 0; --i) {   // back substitution R y = g
             double sacc = gvec[i];
