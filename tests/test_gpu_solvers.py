@@ -210,3 +210,25 @@ def test_critical_grashof_6cube(fvk):
     lam_c = hist[-2]["lam"]
     assert abs(lam_c.real) < 1e-8
     assert abs(lam_c.imag - gold["lambda_critical"][1]) < 1e-7
+
+
+def test_stability_driver_6cube(fvk, capsys):
+    """The command-line stability driver end to end (synthetic base flow,
+    Krylov-Schur, Ritz-residual certificates) on a 6^3 tanh grid, against the
+    finite eigenvalues of the oracle's dense saddle-point pencil on the same
+    base flow."""
+    import json
+    from paper_1905_11601_amd import stability
+    from tests.gpu_util import coords
+    print("case stability driver 6^3", flush=True)
+    rc = stability.main(["--n", "6", "--k", "2", "--m", "24", "--tol", "1e-10",
+                         "--max-restarts", "400"])
+    out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert rc == 0 and out["converged"]
+    assert max(out["ritz_residuals"]) < 1e-9
+    g = Grid(6, kind=TANH, s=1.5)
+    f, c, h = coords(g)
+    U = torch.as_tensor(inputs.synthetic_base(f, c, h, 0))
+    lam_p = dense_pencil_eigs(g, ops.Params(1e6, 0.71), U, 0)
+    lam = np.array([complex(*v) for v in out["eigenvalues"]])
+    assert _match(lam, lam_p[:6], 2) < 1e-9
