@@ -57,6 +57,7 @@ def zero_velocity_walls(grid, vel):
 class Oracle:
     def __init__(self, grid, prm, span_bc, simple_tol=1e-9, simple_cap=10):
         self.grid, self.prm, self.bc = grid, prm, span_bc
+        self.terms = ops.ALL_TERMS   # coupling terms kept in the Krylov operator
         self.tpf = TPF(grid)
         self.tol, self.cap = simple_tol, simple_cap
         self.shape4 = (4,) + grid.shape
@@ -98,7 +99,7 @@ class Oracle:
 
     # ---- the Krylov operator -----------------------------------------------
     def krylov_vec(self, base, x, passes=None, with_info=False):
-        Jx = ops.jacvec(self.grid, self.prm, base, x)
+        Jx = ops.jacvec(self.grid, self.prm, base, x, self.terms)
         v, p, k, dmax = self.simple_project([Jx[0], Jx[1], Jx[2]], passes)
         y = torch.stack(v + [ext_T(self.grid, Jx[3], self.bc)])
         if with_info:
@@ -113,7 +114,7 @@ class Oracle:
 
     def jacvec_T(self, base, y):
         x = torch.zeros(self.shape4, dtype=DT, requires_grad=True)
-        Jx = ops.jacvec(self.grid, self.prm, base, x)
+        Jx = ops.jacvec(self.grid, self.prm, base, x, self.terms)
         (g,) = torch.autograd.grad(Jx, x, grad_outputs=y.to(DT))
         return g.detach()
 

@@ -79,13 +79,14 @@ def faces(grid, a):
 # energy equation, eq. (1) / (8): rows at cells
 # --------------------------------------------------------------------------
 
-def adv_T(grid, a, b):
+def adv_T(grid, a, b, axes=(0, 1, 2)):
     """sum over axes of [a_n b_face]_{face-}^{face+} / h : flux form of (a.grad) b.
 
-    a: three velocity fields (staggered normal components), b: cell field."""
+    a: three velocity fields (staggered normal components), b: cell field;
+    ``axes`` restricts the sum (the term a_al d b / d x_al of each axis al)."""
     R = cells(grid)
     out = 0.0
-    for al in range(3):
+    for al in axes:
         g = grid.ax[al]
         wp, wm = R.coef(g.w, al, 0), R.coef(g.w, al, -1)
         hh = R.coef(g.h, al, 0)
@@ -197,11 +198,26 @@ def residual(grid, prm, base):
     return out
 
 
-def jacvec(grid, prm, base, x):
+# Coupling terms of the linearised eqs (8)-(9) that the mechanism experiment
+# of Sec. 4.2 switches off one at a time (bit i of a term mask):
+TERM_BUOYANCY = 0      # T e_z in the momentum rows
+TERM_U_GRAD_V = 1      # (U.grad) v in the momentum rows
+TERM_V_GRAD_U = 2      # (v.grad) U in the momentum rows
+TERM_U_GRAD_T = 3      # U_a dT/dx_a in the energy rows, bits 3, 4, 5 for a = x, y, z
+TERM_V_GRAD_TH = 6     # v_a dTheta/dx_a in the energy rows, bits 6, 7, 8
+ALL_TERMS = (1 << 9) - 1
+
+
+def jacvec(grid, prm, base, x, terms=ALL_TERMS):
     """J(U, Theta) x, the linearisation of ``residual`` about the base flow:
     velocity rows  nu Lap v - (U.grad) v - (v.grad) U + T e_z      (eq. 9)
     energy rows    kappa Lap T - (U.grad) T - (v.grad) Theta        (eq. 8)
+    ``terms``: bit mask of the coupling terms kept (TERM_*; the viscous and
+    conductive terms are always kept).
     """
+    def on(bit):
+        return bool(terms >> bit & 1)
+
     U = [base[0], base[1], base[2]]
     Th = base[3]
     v = [x[0], x[1], x[2]]
@@ -209,14 +225,23 @@ def jacvec(grid, prm, base, x):
     out = torch.zeros_like(x)
     for al in range(3):
         R = faces(grid, al)
-        r = (prm.nu * lap_mom(grid, al, v[al])
-             - adv_mom(grid, al, U, v[al]) - adv_mom(grid, al, v, U[al]))
-        if al == 2:
+        r = prm.nu * lap_mom(grid, al, v[al])
+        if on(TERM_U_GRAD_V):
+            r = r - adv_mom(grid, al, U, v[al])
+        if on(TERM_V_GRAD_U):
+            r = r - adv_mom(grid, al, v, U[al])
+        if al == 2 and on(TERM_BUOYANCY):
             r = r + prm.b * buoyancy(grid, T)
         out[al][R.idx()] = r
     R = cells(grid)
-    out[3][R.idx()] = (prm.kappa * lap_T(grid, T)
-                       - adv_T(grid, U, T) - adv_T(grid, v, Th))
+    e = prm.kappa * lap_T(grid, T)
+    ax_u = tuple(a for a in range(3) if on(TERM_U_GRAD_T + a))
+    ax_v = tuple(a for a in range(3) if on(TERM_V_GRAD_TH + a))
+    if ax_u:
+        e = e - adv_T(grid, U, T, ax_u)
+    if ax_v:
+        e = e - adv_T(grid, v, Th, ax_v)
+    out[3][R.idx()] = e
     return out
 
 
