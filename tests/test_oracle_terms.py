@@ -112,9 +112,10 @@ def test_energy_switches_are_not_swapped():
     for a in range(3):
         assert changed_fields(full, J(U, x, without(ops.TERM_U_GRAD_T + a))) == []
         assert changed_fields(full, J(U, x, without(ops.TERM_V_GRAD_TH + a))) == [3]
-    # and with a uniform base temperature v.grad Theta vanishes instead
-    U[3].fill_(0.3)
+    # perturbation without velocity: v.grad Theta vanishes, U.grad T does not
+    # (a uniform Theta would not do: in flux form the term is Theta div v)
     x = rand4(G, 17)
+    x[:3].zero_()
     full = J(U, x)
     for a in range(3):
         assert changed_fields(full, J(U, x, without(ops.TERM_V_GRAD_TH + a))) == []
