@@ -77,6 +77,27 @@ fvk_status fvk_set_params(fvk_ctx *ctx, double Gr, double Pr);
 /* Set the three coefficients directly (viscous scaling checks at Gr = 0,
  * derivative operators dA/dGr with b = 0). */
 fvk_status fvk_set_coeffs(fvk_ctx *ctx, double nu, double kappa, double b);
+/* Coupling terms of the linearised eqs (8)-(9) kept in the Jacobian (bit set)
+ * or switched off (bit clear), for the mechanism experiment of Sec. 4.2
+ * (terms nullified one at a time and the stability analysis rerun).  The
+ * viscous and conductive terms are always kept; the residual (fv_residual) is
+ * never affected.  Applies to fv_jacvec, simple_krylov_vec (forward and
+ * transposed) and everything built on them -- newton_step included, so
+ * restore FVK_TERMS_ALL before computing steady states.  Returns
+ * FVK_EINVAL for bits outside FVK_TERMS_ALL. */
+enum {
+    FVK_TERM_BUOYANCY = 1 << 0,   /* T e_z in the momentum rows              */
+    FVK_TERM_U_GRAD_V = 1 << 1,   /* (U.grad) v in the momentum rows         */
+    FVK_TERM_V_GRAD_U = 1 << 2,   /* (v.grad) U in the momentum rows         */
+    FVK_TERM_U_GRAD_T_X = 1 << 3, /* U dT/dx, V dT/dy, W dT/dz: energy rows  */
+    FVK_TERM_U_GRAD_T_Y = 1 << 4,
+    FVK_TERM_U_GRAD_T_Z = 1 << 5,
+    FVK_TERM_V_GRAD_TH_X = 1 << 6, /* u dTheta/dx, v dTheta/dy, w dTheta/dz  */
+    FVK_TERM_V_GRAD_TH_Y = 1 << 7,
+    FVK_TERM_V_GRAD_TH_Z = 1 << 8,
+    FVK_TERMS_ALL = (1 << 9) - 1
+};
+fvk_status fvk_set_terms(fvk_ctx *ctx, int mask);
 fvk_status fvk_set_precision(fvk_ctx *ctx, int prec);
 /* SIMPLE loop control (Sec. 3.1): stop when max |D v| < tol (default 1e-9,
  * the paper's pointwise criterion), at most max_passes passes (default 10). */

@@ -60,7 +60,7 @@ def dense_matrix(fn, n_in, shape_in):
     return np.stack(cols, axis=1)
 
 
-def dense_pencil_eigs(grid, prm, base, span_bc):
+def dense_pencil_eigs(grid, prm, base, span_bc, terms=ops.ALL_TERMS):
     nx, ny, nz = grid.n
     fsize = int(np.prod(grid.shape))
     fidx = [interior_face_index(grid, a) for a in range(3)]
@@ -86,7 +86,7 @@ def dense_pencil_eigs(grid, prm, base, span_bc):
                            np.array(cell_rows)])
 
     def J(x):
-        return ops.jacvec(grid, prm, base, x)
+        return ops.jacvec(grid, prm, base, x, terms)
 
     Jfull = dense_matrix(lambda e: J(torch.as_tensor(Emb @ e.numpy(), dtype=DT)
                                       .reshape((4,) + grid.shape)),

@@ -18,6 +18,11 @@ import numpy as np
 CC, AA = 0, 1
 UNIFORM, SINE, TANH = 0, 1, 2
 FP64, MIXED = 0, 1
+# coupling terms of the linearised operator (fvk_set_terms bit masks)
+TERM_BUOYANCY, TERM_U_GRAD_V, TERM_V_GRAD_U = 1, 2, 4
+TERM_U_GRAD_T = (8, 16, 32)        # U dT/dx, V dT/dy, W dT/dz
+TERM_V_GRAD_TH = (64, 128, 256)    # u dTheta/dx, v dTheta/dy, w dTheta/dz
+TERMS_ALL = 511
 
 
 class FvkError(RuntimeError):
@@ -97,6 +102,11 @@ class Ctx:
 
     def set_coeffs(self, nu, kappa, b):
         self._check(self.lib.fvk_set_coeffs(self.h, float(nu), float(kappa), float(b)))
+
+    def set_terms(self, mask=TERMS_ALL):
+        """Coupling terms kept in the linearised operator (TERM_* bits)."""
+        self._check(self.lib.fvk_set_terms(self.h, int(mask)))
+        self.terms = int(mask)
 
     def set_precision(self, prec):
         self._check(self.lib.fvk_set_precision(self.h, prec))

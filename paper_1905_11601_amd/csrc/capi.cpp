@@ -442,6 +442,22 @@ fvk_status fvk_set_coeffs(fvk_ctx *ctx, double nu, double kappa, double b) {
     return FVK_OK;
 }
 
+fvk_status fvk_set_terms(fvk_ctx *ctx, int mask) {
+    if (!ctx) return FVK_EINVAL;
+    if (mask & ~FVK_TERMS_ALL) return fail(ctx, FVK_EINVAL, "unknown term bits");
+    Coefs &c = ctx->co;
+    auto on = [&](int bit) { return (mask >> bit & 1) ? 1.0 : 0.0; };
+    c.fb = on(0);
+    c.fuv = on(1);
+    c.fvu = on(2);
+    for (int a = 0; a < 3; ++a) {
+        c.fut[a] = on(3 + a);
+        c.fvt[a] = on(6 + a);
+    }
+    c.terms = mask;
+    return FVK_OK;
+}
+
 fvk_status fvk_set_precision(fvk_ctx *ctx, int prec) {
     if (!ctx) return FVK_EINVAL;
     if (prec != FVK_FP64 && prec != FVK_MIXED) return fail(ctx, FVK_EINVAL, "bad precision");

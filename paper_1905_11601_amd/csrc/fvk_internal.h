@@ -33,6 +33,11 @@ struct Geo {
 
 struct Coefs {
     double nu, kappa, b;
+    // factors of the coupling terms of the linearised operator (1 kept, 0
+    // switched off, fvk_set_terms): buoyancy, (U.grad) v, (v.grad) U, and per
+    // axis U_a dT/dx_a and v_a dTheta/dx_a; `terms` is the bit mask
+    double fb = 1.0, fuv = 1.0, fvu = 1.0, fut[3] = {1.0, 1.0, 1.0}, fvt[3] = {1.0, 1.0, 1.0};
+    int terms = FVK_TERMS_ALL;
 };
 
 // Host-side description of one axis (natural indexing, see fvk.h).

@@ -278,9 +278,11 @@ __device__ __forceinline__ AxC axc(const AxisDev &a, int i) {
 }
 
 // field indices in the accessor: perturbation u v w T = 0..3, base = 4..7
-template <int A, int Bt>
+// TERMS: the coupling terms carry the factors of fvk_set_terms (Coefs::f*);
+// without it the expressions are those of the full operator.
+template <int A, int Bt, bool TERMS>
 __device__ __forceinline__ void jrow_tangential(const AxC *C, const TileAcc &X, double wa,
-                                                double &adv, double &lap) {
+                                                const Coefs &c, double &adv, double &lap) {
     const AxC &cB = C[Bt];
     const double wbp = cB.w0, wbm = cB.wm;
     // transporting component Bt at the edges (A-face, Bt-face jb and jb-1)
@@ -294,49 +296,58 @@ __device__ __forceinline__ void jrow_tangential(const AxC *C, const TileAcc &X, 
     const double UpB = AT1(X, 4 + A, Bt, 1), UmB = AT1(X, 4 + A, Bt, -1);
     const double Uap = (1.0 - wbp) * Uc + wbp * UpB, Uam = (1.0 - wbm) * UmB + wbm * Uc;
     const double xap = (1.0 - wbp) * xc + wbp * xpB, xam = (1.0 - wbm) * xmB + wbm * xc;
-    adv += (Utp * xap + xtp * Uap - Utm * xam - xtm * Uam) * cB.ih0;
+    if (TERMS)
+        adv += (c.fuv * (Utp * xap - Utm * xam) + c.fvu * (xtp * Uap - xtm * Uam)) * cB.ih0;
+    else
+        adv += (Utp * xap + xtp * Uap - Utm * xam - xtm * Uam) * cB.ih0;
     lap += ((xpB - xc) * cB.id0 - (xc - xmB) * cB.idm) * cB.ih0;
 }
 
 // nu Lap x_A - N_A(U, x_A) - N_A(x, U_A) (+ b T_f for A = z) at an interior A-face
-template <int A>
-__device__ __forceinline__ double jrow_mom(const AxC *C, const TileAcc &X, double nu,
-                                           double bcoef) {
+template <int A, bool TERMS>
+__device__ __forceinline__ double jrow_mom(const AxC *C, const TileAcc &X, const Coefs &c) {
     const AxC &cA = C[A];
     const double xc = AT1(X, A, A, 0), xp = AT1(X, A, A, 1), xm = AT1(X, A, A, -1);
     const double Uc = AT1(X, 4 + A, A, 0), Up = AT1(X, 4 + A, A, 1), Um = AT1(X, 4 + A, A, -1);
     const double Ubp = 0.5 * (Uc + Up), Ubm = 0.5 * (Um + Uc);
     const double xbp = 0.5 * (xc + xp), xbm = 0.5 * (xm + xc);
-    double adv = (Ubp * xbp - Ubm * xbm + xbp * Ubp - xbm * Ubm) * cA.id0;
+    double adv = TERMS ? (c.fuv * (Ubp * xbp - Ubm * xbm) + c.fvu * (xbp * Ubp - xbm * Ubm)) * cA.id0
+                       : (Ubp * xbp - Ubm * xbm + xbp * Ubp - xbm * Ubm) * cA.id0;
     double lap = ((xp - xc) * cA.ih1 - (xc - xm) * cA.ih0) * cA.id0;
     const double wa = cA.w0;
-    jrow_tangential<A, (A + 1) % 3>(C, X, wa, adv, lap);
-    jrow_tangential<A, (A + 2) % 3>(C, X, wa, adv, lap);
-    double r = nu * lap - adv;
-    if (A == 2) r += bcoef * ((1.0 - wa) * AT1(X, 3, 2, 0) + wa * AT1(X, 3, 2, 1));
+    jrow_tangential<A, (A + 1) % 3, TERMS>(C, X, wa, c, adv, lap);
+    jrow_tangential<A, (A + 2) % 3, TERMS>(C, X, wa, c, adv, lap);
+    double r = c.nu * lap - adv;
+    const double bf = TERMS ? c.b * c.fb : c.b;
+    if (A == 2) r += bf * ((1.0 - wa) * AT1(X, 3, 2, 0) + wa * AT1(X, 3, 2, 1));
     return r;
 }
 
-template <int A>
-__device__ __forceinline__ void jrow_energy_axis(const AxC *C, const TileAcc &X, double &adv,
-                                                 double &lap) {
+template <int A, bool TERMS>
+__device__ __forceinline__ void jrow_energy_axis(const AxC *C, const TileAcc &X, const Coefs &c,
+                                                 double &adv, double &lap) {
     const AxC &cA = C[A];
     const double wp = cA.w0, wm = cA.wm, ih = cA.ih0;
     const double Tc = AT1(X, 3, A, 0), Tp = AT1(X, 3, A, 1), Tm = AT1(X, 3, A, -1);
     const double Hc = AT1(X, 7, A, 0), Hp = AT1(X, 7, A, 1), Hm = AT1(X, 7, A, -1);
     const double Tfp = (1.0 - wp) * Tc + wp * Tp, Tfm = (1.0 - wm) * Tm + wm * Tc;
     const double Hfp = (1.0 - wp) * Hc + wp * Hp, Hfm = (1.0 - wm) * Hm + wm * Hc;
-    adv += (AT1(X, 4 + A, A, 0) * Tfp - AT1(X, 4 + A, A, -1) * Tfm + AT1(X, A, A, 0) * Hfp -
-            AT1(X, A, A, -1) * Hfm) * ih;
+    if (TERMS)
+        adv += (c.fut[A] * (AT1(X, 4 + A, A, 0) * Tfp - AT1(X, 4 + A, A, -1) * Tfm) +
+                c.fvt[A] * (AT1(X, A, A, 0) * Hfp - AT1(X, A, A, -1) * Hfm)) * ih;
+    else
+        adv += (AT1(X, 4 + A, A, 0) * Tfp - AT1(X, 4 + A, A, -1) * Tfm + AT1(X, A, A, 0) * Hfp -
+                AT1(X, A, A, -1) * Hfm) * ih;
     lap += ((Tp - Tc) * cA.id0 - (Tc - Tm) * cA.idm) * ih;
 }
 
-__device__ __forceinline__ double jrow_energy(const AxC *C, const TileAcc &X, double kappa) {
+template <bool TERMS>
+__device__ __forceinline__ double jrow_energy(const AxC *C, const TileAcc &X, const Coefs &c) {
     double adv = 0.0, lap = 0.0;
-    jrow_energy_axis<0>(C, X, adv, lap);
-    jrow_energy_axis<1>(C, X, adv, lap);
-    jrow_energy_axis<2>(C, X, adv, lap);
-    return kappa * lap - adv;
+    jrow_energy_axis<0, TERMS>(C, X, c, adv, lap);
+    jrow_energy_axis<1, TERMS>(C, X, c, adv, lap);
+    jrow_energy_axis<2, TERMS>(C, X, c, adv, lap);
+    return c.kappa * lap - adv;
 }
 
 // LDS-only workgroup barrier: orders LDS traffic without waiting for the
@@ -409,6 +420,7 @@ __device__ __forceinline__ void wall_writes(const Geo &g, double *yv, double *yT
         }
 }
 
+template <bool TERMS>
 __global__ __launch_bounds__(TX *TY, 2) void k_jac_tiled(Geo g, Coefs c, int span_aa,
                                                          const double *__restrict__ base,
                                                          const double *__restrict__ x,
@@ -458,10 +470,10 @@ __global__ __launch_bounds__(TX *TY, 2) void k_jac_tiled(Geo g, Coefs c, int spa
             X.s[1] = lds[k % 3];
             X.s[2] = lds[(k + 1) % 3];
             X.read_centres();
-            const double u = (i <= nx - 1) ? jrow_mom<0>(C, X, c.nu, c.b) : 0.0;
-            const double v = (j <= ny - 1) ? jrow_mom<1>(C, X, c.nu, c.b) : 0.0;
-            const double w = (k <= nz - 1) ? jrow_mom<2>(C, X, c.nu, c.b) : 0.0;
-            const double t = jrow_energy(C, X, c.kappa);
+            const double u = (i <= nx - 1) ? jrow_mom<0, TERMS>(C, X, c) : 0.0;
+            const double v = (j <= ny - 1) ? jrow_mom<1, TERMS>(C, X, c) : 0.0;
+            const double w = (k <= nz - 1) ? jrow_mom<2, TERMS>(C, X, c) : 0.0;
+            const double t = jrow_energy<TERMS>(C, X, c);
             store4(g, yv, yT, i, j, k, u, v, w, t);
             wall_writes(g, yv, yT, i, j, k, span_aa ? t : 0.0, span_aa ? t : 0.0);
             X.shift();
@@ -505,8 +517,13 @@ __device__ __forceinline__ AxT axt(const AxisDev &a, int m) {
                gc(a.id, m),     gc(a.id, m + 1), gc(a.w, m - 1), gc(a.w, m)};
 }
 
-template <int A, class Acc>
-__device__ __forceinline__ double jt_vel(const AxT *T, Coefs c, const Acc &X) {
+template <int A, bool TERMS, class Acc>
+__device__ __forceinline__ double jt_vel(const AxT *T, const Coefs &c, const Acc &X) {
+    // factors of the coupling terms (TERMS); the normal part of the momentum
+    // advection is half (U.grad) v and half (v.grad) U
+    const double fn = TERMS ? 0.5 * (c.fuv + c.fvu) : 1.0;
+    const double f3 = TERMS ? c.fuv : 1.0, f4 = TERMS ? c.fvu : 1.0;
+    const double f5 = TERMS ? c.fvt[A] : 1.0;
     const AxT &TA = T[A];
     const double yc = AT1(X, A, A, 0), ym = AT1(X, A, A, -1), yp = AT1(X, A, A, 1);
     // viscous, normal direction
@@ -515,6 +532,7 @@ __device__ __forceinline__ double jt_vel(const AxT *T, Coefs c, const Acc &X) {
     const double uc = AT1(X, 4 + A, A, 0), um = AT1(X, 4 + A, A, -1), up = AT1(X, 4 + A, A, 1);
     double advT = 0.5 * (um + uc) * (ym * TA.idm - yc * TA.id0) +
                   0.5 * (uc + up) * (yc * TA.id0 - yp * TA.idp);
+    if (TERMS) advT *= fn;
     const double wa = TA.w0;
 #define FVK_JT_TANGENTIAL(Bt)                                                                \
     {                                                                                        \
@@ -529,13 +547,13 @@ __device__ __forceinline__ double jt_vel(const AxT *T, Coefs c, const Acc &X) {
         /* (3) x_A transported in the A-rows along Bt */                                     \
         const double gt_p = yc * TB.ih0 - ypB * TB.ihp;                                      \
         const double gt_m = ymB * TB.ihm - yc * TB.ih0;                                      \
-        advT += ut_p * (1.0 - TB.w0) * gt_p + ut_m * TB.wm * gt_m;                           \
+        advT += f3 * (ut_p * (1.0 - TB.w0) * gt_p + ut_m * TB.wm * gt_m);                    \
         /* (4) x_A transporting U_Bt in the Bt-rows along A */                               \
         const double ybc = AT1(X, Bt, A, 0), ybA = AT1(X, Bt, A, 1);                         \
         const double ybm = AT1(X, Bt, Bt, -1), ybmA = AT2(X, Bt, A, 1, Bt, -1);              \
         const double gq_p = ybc * TA.ih0 - ybA * TA.ihp;                                     \
         const double gq_m = ybm * TA.ih0 - ybmA * TA.ihp;                                    \
-        advT += (1.0 - TB.w0) * ut_p * gq_p + TB.wm * ut_m * gq_m;                           \
+        advT += f4 * ((1.0 - TB.w0) * ut_p * gq_p + TB.wm * ut_m * gq_m);                    \
     }
     FVK_JT_TANGENTIAL((A + 1) % 3)
     FVK_JT_TANGENTIAL((A + 2) % 3)
@@ -543,31 +561,34 @@ __device__ __forceinline__ double jt_vel(const AxT *T, Coefs c, const Acc &X) {
     // (5) x_A transporting Theta in the energy rows
     const double thf = (1.0 - wa) * AT1(X, 7, A, 0) + wa * AT1(X, 7, A, 1);
     const double tc = AT1(X, 3, A, 0), tp = AT1(X, 3, A, 1);
-    advT += thf * (tc * TA.ih0 - tp * TA.ihp);
+    advT += f5 * (thf * (tc * TA.ih0 - tp * TA.ihp));
     return c.nu * lapT - advT;
 }
 
-template <int A, class Acc>
-__device__ __forceinline__ void jt_temp_axis(const AxT &TA, const Acc &X, double tc, double &lapT,
-                                             double &advT) {
+template <int A, bool TERMS, class Acc>
+__device__ __forceinline__ void jt_temp_axis(const AxT &TA, const Acc &X, const Coefs &c, double tc,
+                                             double &lapT, double &advT) {
     const double tm = AT1(X, 3, A, -1), tp = AT1(X, 3, A, 1);
     lapT += -(TA.id0 + TA.idm) * TA.ih0 * tc + TA.idm * TA.ihm * tm + TA.id0 * TA.ihp * tp;
     const double uq = AT1(X, 4 + A, A, 0), uqm = AT1(X, 4 + A, A, -1);
     const double g_p = tc * TA.ih0 - tp * TA.ihp;
     const double g_m = tm * TA.ihm - tc * TA.ih0;
-    advT += uq * (1.0 - TA.w0) * g_p + uqm * TA.wm * g_m;
+    if (TERMS)
+        advT += c.fut[A] * (uq * (1.0 - TA.w0) * g_p + uqm * TA.wm * g_m);
+    else
+        advT += uq * (1.0 - TA.w0) * g_p + uqm * TA.wm * g_m;
 }
 
-template <class Acc>
-__device__ __forceinline__ double jt_temp(const AxT *T, Coefs c, const Acc &X) {
+template <bool TERMS, class Acc>
+__device__ __forceinline__ double jt_temp(const AxT *T, const Coefs &c, const Acc &X) {
     const double tc = AT1(X, 3, 0, 0);
     double lapT = 0.0, advT = 0.0;
-    jt_temp_axis<0>(T[0], X, tc, lapT, advT);
-    jt_temp_axis<1>(T[1], X, tc, lapT, advT);
-    jt_temp_axis<2>(T[2], X, tc, lapT, advT);
+    jt_temp_axis<0, TERMS>(T[0], X, c, tc, lapT, advT);
+    jt_temp_axis<1, TERMS>(T[1], X, c, tc, lapT, advT);
+    jt_temp_axis<2, TERMS>(T[2], X, c, tc, lapT, advT);
     // buoyancy: the w-rows read T at the z-centres k and k+1
     const double buo = (1.0 - T[2].w0) * AT1(X, 2, 2, 0) + T[2].wm * AT1(X, 2, 2, -1);
-    return c.kappa * lapT - advT + c.b * buo;
+    return c.kappa * lapT - advT + (TERMS ? c.b * c.fb : c.b) * buo;
 }
 
 // Tiled transposed Jacobian: the same k-march and LDS plane ring as
@@ -575,6 +596,7 @@ __device__ __forceinline__ double jt_temp(const AxT *T, Coefs c, const Acc &X) {
 // entries are staged already masked (momentum rows on interior faces, energy
 // rows on cells, folded) so the rows read them without tests.  The halo
 // origin is one point below the tile in x and y; planes -1 and nz+2 are zero.
+template <bool TERMS>
 __global__ __launch_bounds__(TX *TY, 2) void k_jacT_tiled(Geo g, Coefs c, int fold,
                                                           const double *__restrict__ base,
                                                           const double *__restrict__ yvel,
@@ -659,10 +681,10 @@ __global__ __launch_bounds__(TX *TY, 2) void k_jacT_tiled(Geo g, Coefs c, int fo
             X.read_centres();
             T[2] = axt(g.ax[2], k);
             const long p = pos(g, i, j, k);
-            x[p] = jt_vel<0>(T, c, X);
-            x[p + F] = jt_vel<1>(T, c, X);
-            x[p + 2 * F] = jt_vel<2>(T, c, X);
-            x[p + 3 * F] = jt_temp(T, c, X);
+            x[p] = jt_vel<0, TERMS>(T, c, X);
+            x[p + F] = jt_vel<1, TERMS>(T, c, X);
+            x[p + 2 * F] = jt_vel<2, TERMS>(T, c, X);
+            x[p + 3 * F] = jt_temp<TERMS>(T, c, X);
             X.shift();
         }
         lds_barrier();
@@ -946,8 +968,11 @@ void launch_jacvec(const Geo &g, Coefs c, int span_aa, int ext, const double *ba
     const int nchunk0 = stencil_chunks(nbx * nby, g.n[2]);
     const int kchunk = (g.n[2] + nchunk0 - 1) / nchunk0;
     const int nchunk = (g.n[2] + kchunk - 1) / kchunk;
-    k_jac_tiled<<<dim3(nbx, nby, nchunk), dim3(TX, TY), 0, st>>>(g, c, span_aa && ext, base, x,
-                                                                  yv, yT, kchunk);
+    const dim3 grid(nbx, nby, nchunk), block(TX, TY);
+    if (c.terms == FVK_TERMS_ALL)
+        k_jac_tiled<false><<<grid, block, 0, st>>>(g, c, span_aa && ext, base, x, yv, yT, kchunk);
+    else
+        k_jac_tiled<true><<<grid, block, 0, st>>>(g, c, span_aa && ext, base, x, yv, yT, kchunk);
 }
 
 void launch_residual(const Geo &g, Coefs c, int span_aa, const double *base, double *F,
@@ -963,8 +988,13 @@ void launch_jacvec_T(const Geo &g, Coefs c, int span_aa, int fold_ext, const dou
     const int nchunk0 = stencil_chunks(nbx * nby, g.np[2]);
     const int kchunk = (g.np[2] + nchunk0 - 1) / nchunk0;
     const int nchunk = (g.np[2] + kchunk - 1) / kchunk;
-    k_jacT_tiled<<<dim3(nbx, nby, nchunk), dim3(TX, TY), 0, st>>>(
-        g, c, fold_ext && span_aa, base, yvel, yT, x, kchunk);
+    const dim3 grid(nbx, nby, nchunk), block(TX, TY);
+    if (c.terms == FVK_TERMS_ALL)
+        k_jacT_tiled<false><<<grid, block, 0, st>>>(g, c, fold_ext && span_aa, base, yvel, yT, x,
+                                                     kchunk);
+    else
+        k_jacT_tiled<true><<<grid, block, 0, st>>>(g, c, fold_ext && span_aa, base, yvel, yT, x,
+                                                    kchunk);
 }
 
 void launch_div(const Geo &g, const double *v, double *div, hipStream_t st, bool win) {

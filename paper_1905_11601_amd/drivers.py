@@ -93,35 +93,53 @@ def total_dlam_dGr(ctx, base, x, y, Up):
 
 
 def critical_gr(ctx, base, Gr0, v0, seed, k=4, m=40, tol=1e-10, gr_rtol=1e-7, max_it=12,
-                log=None):
+                log=None, terms=None):
     """Newton iteration on Gr for Re lambda_lead(Gr) = 0 (the paper's critical
     Grashof number).  ``base`` (in/out) must be a steady state at Gr0.  Each
     iteration: Newton steady state at the current Gr (from the previous one),
     the leading right and left eigenpairs (Krylov-Schur on A and A^T), U', and
-    Gr <- Gr - Re lambda / Re(d lambda / d Gr).  Returns a history list."""
+    Gr <- Gr - Re lambda / Re(d lambda / d Gr).  Returns a history list.
+
+    terms: coupling terms kept in the eigenvalue problem (fvk TERM_* mask, the
+    mechanism experiment of Sec. 4.2); the steady states and U' always use
+    the full equations.
+
+    Where a real eigenvalue crosses zero it meets, near the crossing, the null
+    cluster of the stored-array operator (eigenvalue 0 on the complement of
+    the constraint subspace, purged by krylov_schur): its attainable accuracy
+    is then ~1e-8 and gr_rtol should not be set below the corresponding
+    relative change of Gr.  Oscillatory crossings are not affected."""
+    from . import TERMS_ALL
+    full = TERMS_ALL
+    terms = full if terms is None else terms
     hist = []
     Gr = Gr0
     prev = Gr0
-    for it in range(max_it):
-        if it > 0:
-            # from the steady state at the previous Gr, in steps of at most 1.5x
-            steady_state(ctx, base, Gr, Gr_start=prev, factor=1.5, log=log)
-            prev = Gr
-        ctx.set_params(Gr)
-        r = krylov_schur(ctx, base, k, m, v0, tol=tol)
-        lead = 0
-        lam, x = r.lam[lead], r.X[lead]
-        if lam.imag < 0 and len(r.lam) > 1 and abs(r.lam[1] - np.conj(lam)) < 1e-8 * abs(lam):
-            lam, x = r.lam[1], r.X[1]
-        _, ys = left_eigvecs(ctx, base, [lam], k, m, seed, tol=tol)
-        Up, _ = base_flow_sensitivity(ctx, base)
-        dl = total_dlam_dGr(ctx, base, x, ys[0], Up)
-        hist.append({"Gr": Gr, "lam": lam, "dlam_dGr": dl, "nvec": r.nvec})
-        if log:
-            log(f"critical Gr it {it}: Gr {Gr:.8g} lambda {lam:.6g} dlam/dGr {dl:.4g}")
-        step = -lam.real / dl.real
-        Gr = Gr + step
-        if abs(step) < gr_rtol * abs(Gr):
-            hist.append({"Gr": Gr, "converged": True})
-            break
+    try:
+        for it in range(max_it):
+            ctx.set_terms(full)
+            if it > 0:
+                # from the steady state at the previous Gr, in steps of at most 1.5x
+                steady_state(ctx, base, Gr, Gr_start=prev, factor=1.5, log=log)
+                prev = Gr
+            ctx.set_params(Gr)
+            Up, _ = base_flow_sensitivity(ctx, base)
+            ctx.set_terms(terms)
+            r = krylov_schur(ctx, base, k, m, v0, tol=tol)
+            lead = 0
+            lam, x = r.lam[lead], r.X[lead]
+            if lam.imag < 0 and len(r.lam) > 1 and abs(r.lam[1] - np.conj(lam)) < 1e-8 * abs(lam):
+                lam, x = r.lam[1], r.X[1]
+            _, ys = left_eigvecs(ctx, base, [lam], k, m, seed, tol=tol)
+            dl = total_dlam_dGr(ctx, base, x, ys[0], Up)
+            hist.append({"Gr": Gr, "lam": lam, "dlam_dGr": dl, "nvec": r.nvec})
+            if log:
+                log(f"critical Gr it {it}: Gr {Gr:.8g} lambda {lam:.6g} dlam/dGr {dl:.4g}")
+            step = -lam.real / dl.real
+            Gr = Gr + step
+            if abs(step) < gr_rtol * abs(Gr):
+                hist.append({"Gr": Gr, "converged": True})
+                break
+    finally:
+        ctx.set_terms(full)
     return hist

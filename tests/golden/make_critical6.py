@@ -3,7 +3,9 @@ uniform-grid cube, Pr 0.71, conducting spanwise walls -- the Gr at which the
 real part of the leading (oscillatory) eigenvalue pair of eq. (10) about the
 steady state crosses zero (Sec. 3.1: Newton steady state, then the leading
 eigenvalues, repeated in Gr) -- with the leading eigenvalue and its total
-derivative along the branch of steady states at Gr0 = 1.5e6.
+derivative along the branch of steady states at Gr0 = 1.5e6; and the
+crossing of the eigenvalue problem with the coupling term W dT/dz switched off
+(the mechanism experiment of Sec. 4.2), the steady states unchanged.
 
 Calls only the oracle (and the seeded input module).  Steady states: the
 oracle's Newton (exact sparse solves) with continuation in Gr from the
@@ -44,10 +46,15 @@ def steady(g, U, Gr):
     return U
 
 
-def leading(g, U, Gr):
+# the same crossing with the term W dT/dz switched off in the eigenvalue
+# problem (the mechanism experiment of Sec. 4.2; a real leading eigenvalue)
+MASK_NO_W_DT_DZ = ops.ALL_TERMS & ~(1 << (ops.TERM_U_GRAD_T + 2))
+
+
+def leading(g, U, Gr, terms=ops.ALL_TERMS):
     """Leading eigenvalue (largest real part; the member of a complex pair
     with positive imaginary part)."""
-    lam = dense_pencil_eigs(g, ops.Params(Gr, PR), U, BC)
+    lam = dense_pencil_eigs(g, ops.Params(Gr, PR), U, BC, terms)
     top = lam[np.abs(lam.real - lam[0].real) < 1e-9 * np.abs(lam).max()]
     return top[np.argmax(top.imag)]
 
@@ -68,22 +75,27 @@ def main():
     dlam = (lp - lm) / (2 * d)
     print(f"Gr0 {GR0:g}: lambda {lam0}, d lambda/d Gr (central difference) {dlam}  "
           f"[{time.time() - t0:.0f} s]", flush=True)
-    # secant on Re lambda(Gr) from Gr0 and 2e6 (opposite signs)
-    ga, la = GR0, lam0
-    Ub = steady(g, U0, 1.75e6)
-    gb = 2e6
-    Ub = steady(g, Ub, gb)
-    lb = leading(g, Ub, gb)
-    assert la.real < 0 < lb.real
-    for it in range(30):
-        gc = gb - lb.real * (gb - ga) / (lb.real - la.real)
-        Uc = steady(g, Ub, gc)
-        lc = leading(g, Uc, gc)
-        print(f"secant {it}: Gr {gc:.12g} Re lambda {lc.real:.3e}  [{time.time() - t0:.0f} s]",
-              flush=True)
-        ga, la, gb, lb, Ub = gb, lb, gc, lc, Uc
-        if abs(gb - ga) < 1e-11 * gb:
-            break
+    U2 = steady(g, steady(g, U0, 1.75e6), 2e6)
+
+    def crossing(terms):
+        """secant on Re lambda(Gr) from Gr0 and 2e6 (opposite signs)"""
+        ga, la = GR0, leading(g, U0, GR0, terms)
+        gb, Ub = 2e6, U2
+        lb = leading(g, Ub, gb, terms)
+        assert la.real < 0 < lb.real
+        for it in range(30):
+            gc = gb - lb.real * (gb - ga) / (lb.real - la.real)
+            Uc = steady(g, Ub, gc)
+            lc = leading(g, Uc, gc, terms)
+            print(f"secant {it}: Gr {gc:.12g} Re lambda {lc.real:.3e}  "
+                  f"[{time.time() - t0:.0f} s]", flush=True)
+            ga, la, gb, lb, Ub = gb, lb, gc, lc, Uc
+            if abs(gb - ga) < 1e-11 * gb:
+                break
+        return gb, lb
+
+    gb, lb = crossing(ops.ALL_TERMS)
+    gm, lm = crossing(MASK_NO_W_DT_DZ)
     out = {
         "workload": "6^3 uniform grid, Pr 0.71, conducting walls, oracle steady states",
         "Gr0": GR0,
@@ -92,6 +104,9 @@ def main():
         "fd_step": d,
         "Gr_critical": float(gb),
         "lambda_critical": [float(lb.real), float(lb.imag)],
+        "terms_mask_no_W_dT_dz": MASK_NO_W_DT_DZ,
+        "Gr_critical_no_W_dT_dz": float(gm),
+        "lambda_critical_no_W_dT_dz": [float(lm.real), float(lm.imag)],
     }
     with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "critical_6cube.json"),
               "w") as f:

@@ -177,3 +177,36 @@ def test_arnoldi_step_lagged(fvk, bc, transpose):
         assert rel_err(V[j], torch.as_tensor(Vo[j])) < 1e-9
     G = (V @ V.T).cpu().numpy()
     assert np.max(np.abs(G - np.eye(m + 1))) < 1e-13
+
+
+TERM_MASKS = [
+    ("no_buoyancy", 0b111111110),
+    ("no_w_dTheta_dz", 0b011111111),
+    ("no_u_dTheta_dx", 0b110111111),
+    ("no_momentum_advection", 0b111111001),
+    ("no_U_dT_dx_W_dT_dz", 0b111010111),
+    ("buoyancy_only", 0b000000001),
+]
+
+
+@pytest.mark.parametrize("name,mask", TERM_MASKS, ids=[t[0] for t in TERM_MASKS])
+@pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
+def test_term_switches(fvk, name, mask, bc):
+    """The Krylov operator with coupling terms switched off (fvk_set_terms) and
+    its transpose, against the oracle with the same terms removed."""
+    print(f"case terms {name} bc={bc}", flush=True)
+    g, orc, ctx = setup((10, 9, 11), TANH, 1.5, bc)
+    U = base(g, bc)
+    x = krylov_input(g, orc, 7000)
+    orc.terms = mask
+    ctx.set_terms(mask)
+    ref = orc.krylov_vec(U, x)
+    assert rel_err(ctx.simple_krylov_vec(dev(U), dev(x)), ref) < 1e-10
+    assert rel_err(ctx.fv_jacvec(dev(U), dev(x)), ops.jacvec(g, orc.prm, U, x, mask)) < 1e-10
+    assert rel_err(ctx.fv_jacvec(dev(U), dev(x), transpose=True), orc.jacvec_T(U, x)) < 1e-10
+    refT = orc.krylov_vec_T(U, x)
+    assert rel_err(ctx.simple_krylov_vec(dev(U), dev(x), transpose=True), refT) < 1e-10
+    # switching back restores the full operator
+    ctx.set_terms(fvk.TERMS_ALL)
+    orc.terms = (1 << 9) - 1
+    assert rel_err(ctx.simple_krylov_vec(dev(U), dev(x)), orc.krylov_vec(U, x)) < 1e-10
