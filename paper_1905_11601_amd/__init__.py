@@ -60,6 +60,7 @@ class Ctx:
         self.h = h
         self.span_bc, self.grid_kind, self.s = span_bc, grid, s
         self.Gr, self.Pr, self.prec = Gr, Pr, prec
+        self.terms = TERMS_ALL
         F = ctypes.c_size_t()
         N = ctypes.c_size_t()
         self.lib.fvk_layout(h, None, ctypes.byref(F), ctypes.byref(N))
