@@ -330,7 +330,11 @@ fvk_status fvk_create(fvk_ctx **out, int nx, int ny, int nz, int grid_kind, doub
     if ((st = dalloc(ctx, reinterpret_cast<double **>(&w.tb1), nc)) != FVK_OK) goto bad;
     if ((st = dalloc(ctx, &w.vtmp, nvec(ctx))) != FVK_OK) goto bad;
     if ((st = dalloc(ctx, &w.vtmp2, nvec(ctx))) != FVK_OK) goto bad;
-    w.red_len = std::max<size_t>(size_t(correct_blocks(g)), size_t(multidot_blocks(nvec(ctx))) * 512);
+    // block partials: multi-dot (<= 512 vectors) and the lagged step's
+    // two-vector dots (<= 2 (j + 2) <= 512 rows)
+    w.red_len = std::max<size_t>(size_t(correct_blocks(g)),
+                                 size_t(std::max(multidot_blocks(nvec(ctx)),
+                                                 multidot2_blocks(nvec(ctx)))) * 512);
     if ((st = dalloc(ctx, &w.red, w.red_len)) != FVK_OK) goto bad;
     if ((st = dalloc(ctx, &w.dev_scalars, 4096)) != FVK_OK) goto bad;
     if ((st = dalloc(ctx, &w.dev_counters, 16)) != FVK_OK) goto bad;
@@ -737,7 +741,7 @@ fvk_status arnoldi_step_lagged(fvk_ctx *ctx, const double *base, double *V, size
     const size_t n = nvec(ctx);
     if (ldv < n) return fail(ctx, FVK_EINVAL, "ldv smaller than the vector length");
     const int m2 = j + 2;   // rows v_0..v_{j-1}, slot j, slot j+1
-    const int nb = multidot_blocks(n);
+    const int nb = multidot2_blocks(n);
     if (size_t(nb) * 2 * m2 > ctx->ws.red_len || 2 * m2 + 8 > 4096 || 2 * j > int(ctx->ws.coef_len))
         return fail(ctx, FVK_EINVAL, "Krylov dimension too large");
     double *x = V + size_t(j) * ldv, *w = V + size_t(j + 1) * ldv;
@@ -746,8 +750,7 @@ fvk_status arnoldi_step_lagged(fvk_ctx *ctx, const double *base, double *V, size
     hipStream_t st = ctx->stream;
     double *dots = ctx->ws.dev_scalars + 8;
     timing_begin(ctx, FVK_STAGE_ORTHO);
-    launch_multidot2(V, ldv, m2, x, w, n, ctx->ws.red, nb, st);
-    launch_reduce_partials(ctx->ws.red, nb, 2 * m2, dots, 0, st);
+    launch_multidot2(V, ldv, m2, x, w, n, ctx->ws.red, nb, dots, st);
     timing_end(ctx, FVK_STAGE_ORTHO);
     CHECK_LAUNCH(ctx);
     std::vector<double> d(2 * m2);

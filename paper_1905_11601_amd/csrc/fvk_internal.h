@@ -168,8 +168,9 @@ bool tpf_fuses_div(const fvk_ctx *ctx);
 int multidot_blocks(size_t n);
 void launch_multidot(const double *V, size_t ldv, int m, const double *w, size_t n,
                      double *partials, int nblk, hipStream_t st);
+int multidot2_blocks(size_t n);
 void launch_multidot2(const double *V, size_t ldv, int m, const double *x, const double *y,
-                      size_t n, double *partials, int nblk, hipStream_t st);
+                      size_t n, double *partials, int nblk, double *out, hipStream_t st);
 void launch_update2(double *x, double *y, const double *V, size_t ldv, int m, const double *a_dev,
                     const double *b_dev, double c1, double c2, double c3, size_t n,
                     hipStream_t st);

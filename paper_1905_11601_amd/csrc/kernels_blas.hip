@@ -3,6 +3,8 @@
 // reductions.  All reductions use a fixed tree (wavefront shuffles, then the
 // block, then a separate pass over the block partials in index order), so
 // results are bitwise reproducible run to run.
+#include <algorithm>
+
 #include "fvk_internal.h"
 
 namespace fvk {
@@ -50,29 +52,46 @@ __global__ __launch_bounds__(NT) void k_multidot(const double *__restrict__ V, s
     }
 }
 
-// Dot products of m rows of V with two vectors x and y in one pass over V:
-// partials[blk * 2m + 2q + r] = sum over this block's rows of V_q[i] * (r ? y : x)[i].
-constexpr int GROUP2 = 16;
+// Dot products of m rows of V with two vectors x and y in one pass over V.
+// Block b owns the contiguous tile [b T2, (b+1) T2) of the entries (the
+// whole chip streams neighbouring tiles, as the update kernel does) and walks
+// its rows in groups of GROUP2, re-reading the tile of x and y from L2:
+// partials[(2q + r) * nblk + b] = sum over the tile of V_q[i] * (r ? y : x)[i].
+constexpr int GROUP2 = 8, E2 = 16, U2 = 4, T2 = NT * E2;
 __global__ __launch_bounds__(NT) void k_multidot2(const double *__restrict__ V, size_t ldv, int m,
                                                   const double *__restrict__ x,
                                                   const double *__restrict__ y, size_t n,
-                                                  size_t chunk, double *__restrict__ partials) {
+                                                  size_t tile, int nblk,
+                                                  double *__restrict__ partials) {
     __shared__ double sh[2 * GROUP2][NT / 64];
-    const size_t r0 = size_t(blockIdx.x) * chunk;
-    const size_t r1 = min(n, r0 + chunk);
+    const size_t r0 = size_t(blockIdx.x) * tile;
+    const size_t r1 = min(n, r0 + tile);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int q0 = 0; q0 < m; q0 += GROUP2) {
         double ax[GROUP2], ay[GROUP2];
 #pragma unroll
         for (int t = 0; t < GROUP2; ++t) ax[t] = ay[t] = 0.0;
-        for (size_t r = r0 + threadIdx.x; r < r1; r += NT) {
-            const double xr = x[r], yr = y[r];
+        // U2 entries per step, loads issued together (clamped addresses; the
+        // entries past the tile get zero weights)
+        for (size_t rb = r0; rb < r1; rb += size_t(U2) * NT) {
+            double xr[U2], yr[U2], v[U2][GROUP2];
 #pragma unroll
-            for (int t = 0; t < GROUP2; ++t)
-                if (q0 + t < m) {
-                    const double v = V[size_t(q0 + t) * ldv + r];
-                    ax[t] += v * xr;
-                    ay[t] += v * yr;
+            for (int u = 0; u < U2; ++u) {
+                const size_t r = rb + size_t(u) * NT + threadIdx.x;
+                const size_t rc = min(r, r1 - 1);
+                const bool in = r < r1;
+                xr[u] = in ? x[rc] : 0.0;
+                yr[u] = in ? y[rc] : 0.0;
+#pragma unroll
+                for (int t = 0; t < GROUP2; ++t)
+                    v[u][t] = V[size_t(min(q0 + t, m - 1)) * ldv + rc];
+            }
+#pragma unroll
+            for (int u = 0; u < U2; ++u)
+#pragma unroll
+                for (int t = 0; t < GROUP2; ++t) {
+                    ax[t] += v[u][t] * xr[u];
+                    ay[t] += v[u][t] * yr[u];
                 }
         }
 #pragma unroll
@@ -87,9 +106,26 @@ __global__ __launch_bounds__(NT) void k_multidot2(const double *__restrict__ V, 
         if (threadIdx.x < 2 * GROUP2 && q0 + threadIdx.x / 2 < m) {
             double s = 0.0;
             for (int q = 0; q < NT / 64; ++q) s += sh[threadIdx.x][q];
-            partials[size_t(blockIdx.x) * 2 * m + 2 * q0 + threadIdx.x] = s;
+            partials[size_t(2 * q0 + threadIdx.x) * nblk + blockIdx.x] = s;
         }
         __syncthreads();
+    }
+}
+
+// out[q] = sum_b partials[q * nblk + b] (rows of block partials, contiguous)
+__global__ void k_reduce_rows(const double *__restrict__ partials, int nblk,
+                              double *__restrict__ out) {
+    const int q = blockIdx.x;
+    __shared__ double sh[NT / 64];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += NT) s += partials[size_t(q) * nblk + b];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < NT / 64; ++k) t += sh[k];
+        out[q] = t;
     }
 }
 
@@ -261,10 +297,22 @@ void launch_multidot(const double *V, size_t ldv, int m, const double *w, size_t
     k_multidot<<<nblk, NT, 0, st>>>(V, ldv, m, w, n, chunk, partials);
 }
 
+// One resident round of the two-vector dot kernel (three 256-thread blocks per
+// compute unit at its register count, 256 compute units): a second, partial
+// round would leave most of the chip idle.
+// tiles of T2 entries, at most 32768 of them (longer tiles beyond that)
+int multidot2_blocks(size_t n) {
+    const size_t b = (n + T2 - 1) / T2;
+    return int(std::max<size_t>(1, std::min<size_t>(b, 32768)));
+}
+
+// partials: 2 m rows of nblk block sums; out: the 2 m dot products
+// (out[2q] = V_q . x, out[2q + 1] = V_q . y)
 void launch_multidot2(const double *V, size_t ldv, int m, const double *x, const double *y,
-                      size_t n, double *partials, int nblk, hipStream_t st) {
-    const size_t chunk = (n + nblk - 1) / nblk;
-    k_multidot2<<<nblk, NT, 0, st>>>(V, ldv, m, x, y, n, chunk, partials);
+                      size_t n, double *partials, int nblk, double *out, hipStream_t st) {
+    const size_t tile = (n + nblk - 1) / nblk;
+    k_multidot2<<<nblk, NT, 0, st>>>(V, ldv, m, x, y, n, tile, nblk, partials);
+    k_reduce_rows<<<2 * m, NT, 0, st>>>(partials, nblk, out);
 }
 
 void launch_update2(double *x, double *y, const double *V, size_t ldv, int m, const double *a_dev,
