@@ -10,6 +10,7 @@
 // equation are the interior cells.  Forward kernels write every stored entry
 // (0 where the operator has no row).
 #include <algorithm>
+#include <type_traits>
 
 #include "fvk_internal.h"
 
@@ -361,32 +362,71 @@ __device__ __forceinline__ void lds_barrier() {
 constexpr int NT_T = TX * TY;
 constexpr int PER_T = (PLANE + NT_T - 1) / NT_T;   // plane entries per thread per field
 
-// global -> registers for one plane (tile + halo) of all fields.  Branch-free
-// and use-free: every entry loads a clamped (valid) address, and the entries
-// outside the stored box are zeroed only in put_plane, one step later -- so
-// the NF * PER_T loads stay in flight across the whole step.
-__device__ __forceinline__ void fetch_plane(const Geo &g, const double *const *fp, int i0, int j0,
-                                            int kk, int tid, double (&reg)[NF][PER_T]) {
-    const long base = long(kk) * g.s[2];
+// Plane-relative addressing for the k-march through buffer resources: the
+// descriptor of plane kk of a field (base, size in bytes) is block-uniform and
+// lives in scalar registers, and a thread's in-plane byte offsets are fixed
+// along the march (a plane is at most 1026^2 entries, well inside 32 bits), so
+// no load or store needs per-access 64-bit address arithmetic.  A read at an
+// offset past the descriptor's size returns 0 (buffer range checking): the
+// halo entries outside the stored box are given such an offset, so they arrive
+// already zeroed and the staging needs no mask.
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr unsigned kOutside = 0x80000000u;   // beyond any plane: reads as 0
+
+__device__ __forceinline__ Rsrc plane_rsrc(const double *field, long plane_off, int bytes) {
+    // dword 3 of a raw (untyped, stride 0) buffer descriptor on gfx9-family parts
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(field + plane_off), short(0),
+                                             bytes, 0x00020000);
+}
+__device__ __forceinline__ double bload(Rsrc r, unsigned off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, int(off), 0, 0));
+}
+__device__ __forceinline__ void bstore(Rsrc r, unsigned off, double v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, int(off), 0, 0);
+}
+
+// in-plane byte offsets of the thread's staged entries (kOutside outside the box)
+struct PlaneSlots {
+    unsigned off[PER_T];
+};
+
+__device__ __forceinline__ PlaneSlots plane_slots(const Geo &g, int i0, int j0, int tid) {
+    PlaneSlots P;
 #pragma unroll
     for (int q = 0; q < PER_T; ++q) {
         const int r = min(tid + q * NT_T, PLANE - 1);
         const int gi = i0 + r % TWP, gj = j0 + r / TWP;
-        const long off = base + long(min(gj, g.np[1] - 1)) * g.s[1] + min(gi, g.np[0] - 1);
+        const bool ok = gi < g.np[0] && gj < g.np[1];
+        P.off[q] = ok ? unsigned(gj * int(g.s[1]) + gi) * 8u : kOutside;
+    }
+    return P;
+}
+
+// global -> registers for one plane (tile + halo) of all fields.  Use-free:
+// the NF * PER_T loads stay in flight across the whole step and are consumed
+// only by put_plane_rel, one step later.
+__device__ __forceinline__ void fetch_plane_rel(const Geo &g, const double *const *fp,
+                                                const PlaneSlots &P, int kk,
+                                                double (&reg)[NF][PER_T]) {
+    const long base = long(kk) * g.s[2];
+    const int bytes = int(g.s[2]) * 8;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) reg[f][q] = fp[f][off];
+    for (int f = 0; f < NF; ++f) {
+        const Rsrc r = plane_rsrc(fp[f], base, bytes);
+#pragma unroll
+        for (int q = 0; q < PER_T; ++q) reg[f][q] = bload(r, P.off[q]);
     }
 }
 
-__device__ __forceinline__ void put_plane(const Geo &g, int i0, int j0, double *dst, int tid,
-                                          const double (&reg)[NF][PER_T]) {
+__device__ __forceinline__ void put_plane_rel(double *dst, int tid,
+                                              const double (&reg)[NF][PER_T]) {
 #pragma unroll
     for (int q = 0; q < PER_T; ++q) {
         const int r = tid + q * NT_T;
-        const bool ok = i0 + r % TWP < g.np[0] && j0 + r / TWP < g.np[1];
         if (r < PLANE) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) dst[f * PLANE + r] = ok ? reg[f][q] : 0.0;
+            for (int f = 0; f < NF; ++f) dst[f * PLANE + r] = reg[f][q];
         }
     }
 }
@@ -420,6 +460,30 @@ __device__ __forceinline__ void wall_writes(const Geo &g, double *yv, double *yT
         }
 }
 
+// wall_writes for plane k through the plane's four output descriptors
+// (u v w T); `own` is the in-plane byte offset of (i, j)
+__device__ __forceinline__ void wall_writes_rel(const Geo &g, const Rsrc *r4, unsigned own, int i,
+                                                int j, double t_aa_lo, double t_aa_hi) {
+    const int nx = g.n[0], ny = g.n[1];
+    const int dis[3] = {0, i == 1 ? -1 : 0, i == nx ? 1 : 0};
+    const int djs[3] = {0, j == 1 ? -1 : 0, j == ny ? 1 : 0};
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if ((a == 0 && b == 0) || (a > 0 && dis[a] == 0) || (b > 0 && djs[b] == 0)) continue;
+            const int di = dis[a], dj = djs[b];
+            double t = 0.0;
+            if (di == 0 && dj == -1) t = t_aa_lo;
+            if (di == 0 && dj == 1) t = t_aa_hi;
+            const unsigned o = own + unsigned((dj * int(g.s[1]) + di) * 8);
+            bstore(r4[0], o, 0.0);
+            bstore(r4[1], o, 0.0);
+            bstore(r4[2], o, 0.0);
+            bstore(r4[3], o, t);
+        }
+}
+
 template <bool TERMS>
 __global__ __launch_bounds__(TX *TY, 2) void k_jac_tiled(Geo g, Coefs c, int span_aa,
                                                          const double *__restrict__ base,
@@ -448,22 +512,26 @@ __global__ __launch_bounds__(TX *TY, 2) void k_jac_tiled(Geo g, Coefs c, int spa
     AxC C[3];
     C[0] = axc(g.ax[0], min(i, nx));
     C[1] = axc(g.ax[1], min(j, ny));
+    const PlaneSlots P = plane_slots(g, i0, j0, tid);
+    // this thread's output point within a plane (bytes; unused when !act)
+    const unsigned own = unsigned(min(j, ny) * int(g.s[1]) + min(i, nx)) * 8u;
+    const int pbytes = int(g.s[2]) * 8;
     double reg[NF][PER_T];
-    fetch_plane(g, fp, i0, j0, kb - 1, tid, reg);
-    put_plane(g, i0, j0, lds[(kb - 1) % 3], tid, reg);
-    fetch_plane(g, fp, i0, j0, kb, tid, reg);
-    put_plane(g, i0, j0, lds[kb % 3], tid, reg);
-    fetch_plane(g, fp, i0, j0, kb + 1, tid, reg);
+    fetch_plane_rel(g, fp, P, kb - 1, reg);
+    put_plane_rel(lds[(kb - 1) % 3], tid, reg);
+    fetch_plane_rel(g, fp, P, kb, reg);
+    put_plane_rel(lds[kb % 3], tid, reg);
+    fetch_plane_rel(g, fp, P, kb + 1, reg);
     TileAcc X;
     X.c = (ty + 1) * TWP + tx + 1;
     lds_barrier();
     if (act) X.first_centres(lds[(kb - 1) % 3], lds[kb % 3]);
     for (int k = kb; k <= ke; ++k) {
-        put_plane(g, i0, j0, lds[(k + 1) % 3], tid, reg);
+        put_plane_rel(lds[(k + 1) % 3], tid, reg);
         lds_barrier();
         // always issued (clamped to the last stored plane) so that the count
         // of loads in flight after this point is the same on every step
-        fetch_plane(g, fp, i0, j0, min(k + 2, nz + 1), tid, reg);
+        fetch_plane_rel(g, fp, P, min(k + 2, nz + 1), reg);
         C[2] = axc(g.ax[2], k);
         if (act) {
             X.s[0] = lds[(k - 1) % 3];
@@ -474,8 +542,14 @@ __global__ __launch_bounds__(TX *TY, 2) void k_jac_tiled(Geo g, Coefs c, int spa
             const double v = (j <= ny - 1) ? jrow_mom<1, TERMS>(C, X, c) : 0.0;
             const double w = (k <= nz - 1) ? jrow_mom<2, TERMS>(C, X, c) : 0.0;
             const double t = jrow_energy<TERMS>(C, X, c);
-            store4(g, yv, yT, i, j, k, u, v, w, t);
-            wall_writes(g, yv, yT, i, j, k, span_aa ? t : 0.0, span_aa ? t : 0.0);
+            const long pk = long(k) * g.s[2];
+            const Rsrc r4[4] = {plane_rsrc(yv, pk, pbytes), plane_rsrc(yv + F, pk, pbytes),
+                                plane_rsrc(yv + 2 * F, pk, pbytes), plane_rsrc(yT, pk, pbytes)};
+            bstore(r4[0], own, u);
+            bstore(r4[1], own, v);
+            bstore(r4[2], own, w);
+            bstore(r4[3], own, t);
+            wall_writes_rel(g, r4, own, i, j, span_aa ? t : 0.0, span_aa ? t : 0.0);
             X.shift();
         }
         lds_barrier();
