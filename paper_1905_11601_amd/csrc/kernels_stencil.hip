@@ -210,13 +210,24 @@ __global__ __launch_bounds__(BX *BY) void k_jac(Geo g, Coefs c, int span_aa,
 // chunk.  Blocks are remapped so that each XCD (one L2) gets a contiguous range
 // of tiles and reuses the halo rows of its neighbours.
 
-constexpr int TX = 64, TY = 4, TWP = TX + 2, THP = TY + 2, PLANE = TWP * THP, NF = 8;
+constexpr int TX = 64, TWP = TX + 2, NF = 8;
+// A tile of TX x H interior points: its plane with the one-point halo, the
+// threads of its block and the staged entries per thread and field.
+template <int H>
+struct Tile {
+    static constexpr int TY = H, THP = H + 2, PLANE = TWP * THP, NT = TX * H,
+                         PER = (PLANE + NT - 1) / NT;
+};
+// the transposed kernel's tile (64 x 4)
+constexpr int TY = 4, THP = TY + 2, PLANE = TWP * THP;
 
 // The thread's own column (offset 0 in i and j) at planes k-1, k, k+1 is
 // carried in registers along the k-march: each centre value is read from LDS
 // once (when its plane is staged) instead of at every use, which halves the
 // LDS reads per point.
+template <int PL>
 struct TileAcc {
+    static constexpr int PLANE = PL;
     const double *s[3];   // planes k-1, k, k+1
     int c;                // LDS offset of this thread's centre point
     double cen[3][NF];    // centres of planes k-1, k, k+1
@@ -281,8 +292,8 @@ __device__ __forceinline__ AxC axc(const AxisDev &a, int i) {
 // field indices in the accessor: perturbation u v w T = 0..3, base = 4..7
 // TERMS: the coupling terms carry the factors of fvk_set_terms (Coefs::f*);
 // without it the expressions are those of the full operator.
-template <int A, int Bt, bool TERMS>
-__device__ __forceinline__ void jrow_tangential(const AxC *C, const TileAcc &X, double wa,
+template <int A, int Bt, bool TERMS, class Acc>
+__device__ __forceinline__ void jrow_tangential(const AxC *C, const Acc &X, double wa,
                                                 const Coefs &c, double &adv, double &lap) {
     const AxC &cB = C[Bt];
     const double wbp = cB.w0, wbm = cB.wm;
@@ -305,8 +316,8 @@ __device__ __forceinline__ void jrow_tangential(const AxC *C, const TileAcc &X, 
 }
 
 // nu Lap x_A - N_A(U, x_A) - N_A(x, U_A) (+ b T_f for A = z) at an interior A-face
-template <int A, bool TERMS>
-__device__ __forceinline__ double jrow_mom(const AxC *C, const TileAcc &X, const Coefs &c) {
+template <int A, bool TERMS, class Acc>
+__device__ __forceinline__ double jrow_mom(const AxC *C, const Acc &X, const Coefs &c) {
     const AxC &cA = C[A];
     const double xc = AT1(X, A, A, 0), xp = AT1(X, A, A, 1), xm = AT1(X, A, A, -1);
     const double Uc = AT1(X, 4 + A, A, 0), Up = AT1(X, 4 + A, A, 1), Um = AT1(X, 4 + A, A, -1);
@@ -324,8 +335,8 @@ __device__ __forceinline__ double jrow_mom(const AxC *C, const TileAcc &X, const
     return r;
 }
 
-template <int A, bool TERMS>
-__device__ __forceinline__ void jrow_energy_axis(const AxC *C, const TileAcc &X, const Coefs &c,
+template <int A, bool TERMS, class Acc>
+__device__ __forceinline__ void jrow_energy_axis(const AxC *C, const Acc &X, const Coefs &c,
                                                  double &adv, double &lap) {
     const AxC &cA = C[A];
     const double wp = cA.w0, wm = cA.wm, ih = cA.ih0;
@@ -342,8 +353,8 @@ __device__ __forceinline__ void jrow_energy_axis(const AxC *C, const TileAcc &X,
     lap += ((Tp - Tc) * cA.id0 - (Tc - Tm) * cA.idm) * ih;
 }
 
-template <bool TERMS>
-__device__ __forceinline__ double jrow_energy(const AxC *C, const TileAcc &X, const Coefs &c) {
+template <bool TERMS, class Acc>
+__device__ __forceinline__ double jrow_energy(const AxC *C, const Acc &X, const Coefs &c) {
     double adv = 0.0, lap = 0.0;
     jrow_energy_axis<0, TERMS>(C, X, c, adv, lap);
     jrow_energy_axis<1, TERMS>(C, X, c, adv, lap);
@@ -360,7 +371,7 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 constexpr int NT_T = TX * TY;
-constexpr int PER_T = (PLANE + NT_T - 1) / NT_T;   // plane entries per thread per field
+constexpr int PER_T = (PLANE + NT_T - 1) / NT_T;   // plane entries per thread per field (64 x 4)
 
 // Plane-relative addressing for the k-march through buffer resources: the
 // descriptor of plane kk of a field (base, size in bytes) is block-uniform and
@@ -387,15 +398,17 @@ __device__ __forceinline__ void bstore(Rsrc r, unsigned off, double v) {
 }
 
 // in-plane byte offsets of the thread's staged entries (kOutside outside the box)
+template <class Tl>
 struct PlaneSlots {
-    unsigned off[PER_T];
+    unsigned off[Tl::PER];
 };
 
-__device__ __forceinline__ PlaneSlots plane_slots(const Geo &g, int i0, int j0, int tid) {
-    PlaneSlots P;
+template <class Tl>
+__device__ __forceinline__ PlaneSlots<Tl> plane_slots(const Geo &g, int i0, int j0, int tid) {
+    PlaneSlots<Tl> P;
 #pragma unroll
-    for (int q = 0; q < PER_T; ++q) {
-        const int r = min(tid + q * NT_T, PLANE - 1);
+    for (int q = 0; q < Tl::PER; ++q) {
+        const int r = min(tid + q * Tl::NT, Tl::PLANE - 1);
         const int gi = i0 + r % TWP, gj = j0 + r / TWP;
         const bool ok = gi < g.np[0] && gj < g.np[1];
         P.off[q] = ok ? unsigned(gj * int(g.s[1]) + gi) * 8u : kOutside;
@@ -404,29 +417,32 @@ __device__ __forceinline__ PlaneSlots plane_slots(const Geo &g, int i0, int j0, 
 }
 
 // global -> registers for one plane (tile + halo) of all fields.  Use-free:
-// the NF * PER_T loads stay in flight across the whole step and are consumed
-// only by put_plane_rel, one step later.
+// the NF * PER loads stay in flight across the whole step and are consumed
+// only by put_plane_rel, one step later.  Slots past the plane are skipped.
+template <class Tl>
 __device__ __forceinline__ void fetch_plane_rel(const Geo &g, const double *const *fp,
-                                                const PlaneSlots &P, int kk,
-                                                double (&reg)[NF][PER_T]) {
+                                                const PlaneSlots<Tl> &P, int kk, int tid,
+                                                double (&reg)[NF][Tl::PER]) {
     const long base = long(kk) * g.s[2];
     const int bytes = int(g.s[2]) * 8;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         const Rsrc r = plane_rsrc(fp[f], base, bytes);
 #pragma unroll
-        for (int q = 0; q < PER_T; ++q) reg[f][q] = bload(r, P.off[q]);
+        for (int q = 0; q < Tl::PER; ++q)
+            if (q == 0 || tid + q * Tl::NT < Tl::PLANE) reg[f][q] = bload(r, P.off[q]);
     }
 }
 
+template <class Tl>
 __device__ __forceinline__ void put_plane_rel(double *dst, int tid,
-                                              const double (&reg)[NF][PER_T]) {
+                                              const double (&reg)[NF][Tl::PER]) {
 #pragma unroll
-    for (int q = 0; q < PER_T; ++q) {
-        const int r = tid + q * NT_T;
-        if (r < PLANE) {
+    for (int q = 0; q < Tl::PER; ++q) {
+        const int r = tid + q * Tl::NT;
+        if (r < Tl::PLANE) {
 #pragma unroll
-            for (int f = 0; f < NF; ++f) dst[f * PLANE + r] = reg[f][q];
+            for (int f = 0; f < NF; ++f) dst[f * Tl::PLANE + r] = reg[f][q];
         }
     }
 }
@@ -484,13 +500,14 @@ __device__ __forceinline__ void wall_writes_rel(const Geo &g, const Rsrc *r4, un
         }
 }
 
-template <bool TERMS>
-__global__ __launch_bounds__(TX *TY, 2) void k_jac_tiled(Geo g, Coefs c, int span_aa,
+template <bool TERMS, int H>
+__global__ __launch_bounds__(TX *H, 8 / H) void k_jac_tiled(Geo g, Coefs c, int span_aa,
                                                          const double *__restrict__ base,
                                                          const double *__restrict__ x,
                                                          double *__restrict__ yv,
                                                          double *__restrict__ yT, int kchunk) {
-    __shared__ double lds[3][NF * PLANE];
+    using Tl = Tile<H>;
+    __shared__ double lds[3][NF * Tl::PLANE];
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
     // XCD-aware tile order: hardware block b runs on XCD b % 8; give each XCD a
     // contiguous range of logical tiles
@@ -500,7 +517,7 @@ __global__ __launch_bounds__(TX *TY, 2) void k_jac_tiled(Geo g, Coefs c, int spa
     int lb = b;
     if ((nb % 8) == 0) lb = (b % 8) * (nb / 8) + b / 8;
     const int bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
-    const int i0 = bx * TX, j0 = by * TY;          // halo origin (interior starts at +1)
+    const int i0 = bx * TX, j0 = by * H;           // halo origin (interior starts at +1)
     const int i = i0 + 1 + tx, j = j0 + 1 + ty;
     const int kb = 1 + bz * kchunk;
     const int ke = min(g.n[2], kb + kchunk - 1);
@@ -512,26 +529,26 @@ __global__ __launch_bounds__(TX *TY, 2) void k_jac_tiled(Geo g, Coefs c, int spa
     AxC C[3];
     C[0] = axc(g.ax[0], min(i, nx));
     C[1] = axc(g.ax[1], min(j, ny));
-    const PlaneSlots P = plane_slots(g, i0, j0, tid);
+    const PlaneSlots<Tl> P = plane_slots<Tl>(g, i0, j0, tid);
     // this thread's output point within a plane (bytes; unused when !act)
     const unsigned own = unsigned(min(j, ny) * int(g.s[1]) + min(i, nx)) * 8u;
     const int pbytes = int(g.s[2]) * 8;
-    double reg[NF][PER_T];
-    fetch_plane_rel(g, fp, P, kb - 1, reg);
-    put_plane_rel(lds[(kb - 1) % 3], tid, reg);
-    fetch_plane_rel(g, fp, P, kb, reg);
-    put_plane_rel(lds[kb % 3], tid, reg);
-    fetch_plane_rel(g, fp, P, kb + 1, reg);
-    TileAcc X;
+    double reg[NF][Tl::PER];
+    fetch_plane_rel(g, fp, P, kb - 1, tid, reg);
+    put_plane_rel<Tl>(lds[(kb - 1) % 3], tid, reg);
+    fetch_plane_rel(g, fp, P, kb, tid, reg);
+    put_plane_rel<Tl>(lds[kb % 3], tid, reg);
+    fetch_plane_rel(g, fp, P, kb + 1, tid, reg);
+    TileAcc<Tl::PLANE> X;
     X.c = (ty + 1) * TWP + tx + 1;
     lds_barrier();
     if (act) X.first_centres(lds[(kb - 1) % 3], lds[kb % 3]);
     for (int k = kb; k <= ke; ++k) {
-        put_plane_rel(lds[(k + 1) % 3], tid, reg);
+        put_plane_rel<Tl>(lds[(k + 1) % 3], tid, reg);
         lds_barrier();
         // always issued (clamped to the last stored plane) so that the count
         // of loads in flight after this point is the same on every step
-        fetch_plane_rel(g, fp, P, min(k + 2, nz + 1), reg);
+        fetch_plane_rel(g, fp, P, min(k + 2, nz + 1), tid, reg);
         C[2] = axc(g.ax[2], k);
         if (act) {
             X.s[0] = lds[(k - 1) % 3];
@@ -692,6 +709,7 @@ __global__ __launch_bounds__(TX *TY, 2) void k_jacT_tiled(Geo g, Coefs c, int fo
         const int kc = min(max(kk, 0), np2 - 1);
 #pragma unroll
         for (int q = 0; q < PER_T; ++q) {
+            if (q > 0 && tid + q * NT_T >= PLANE) continue;
             const int r = min(tid + q * NT_T, PLANE - 1);
             const int gi = min(max(i0 + r % TWP, 0), g.np[0] - 1);
             const int gj = min(max(j0 + r / TWP, 0), g.np[1] - 1);
@@ -737,7 +755,7 @@ __global__ __launch_bounds__(TX *TY, 2) void k_jacT_tiled(Geo g, Coefs c, int fo
     fetch(kb);
     stage(kb, lds[kb % 3]);
     fetch(kb + 1);
-    TileAcc X;
+    TileAcc<PLANE> X;
     X.c = (ty + 1) * TWP + tx + 1;
     AxT T[3];
     T[0] = axt(g.ax[0], min(i, g.np[0] - 1));
@@ -1028,25 +1046,41 @@ int correct_blocks(const Geo &g) {
 // k-chunks of the tiled stencils: marches of ~10 planes while that keeps the
 // grid at <= 2048 blocks, else 512 / tiles chunks (at least 2) -- measured on
 // 100^3, 160^3 and 256^3
-static int stencil_chunks(int tiles, int nk) {
+// k-chunks per tile column: marches of ~10 planes while the grid is small,
+// else just enough chunks for `per_cu` resident blocks on each of the 256 CUs
+static int stencil_chunks(int tiles, int nk, int per_cu) {
     int nchunk = (nk + 9) / 10;
-    if (long(tiles) * nchunk > 2048) nchunk = std::max(2, 512 / std::max(1, tiles));
+    if (long(tiles) * nchunk > 1024L * per_cu)
+        nchunk = std::max(per_cu, 256 * per_cu / std::max(1, tiles));
     return std::max(1, std::min(nchunk, nk));
+}
+
+template <int H>
+static void launch_jac_tiled(const Geo &g, Coefs c, int span_aa, const double *base,
+                             const double *x, double *yv, double *yT, hipStream_t st) {
+    // tiles of the interior plane; k split into chunks so the grid fills the
+    // chip (8 / H resident blocks per CU) while each block keeps a long k-march
+    const int nbx = (g.n[0] + TX - 1) / TX, nby = (g.n[1] + H - 1) / H;
+    const int nchunk0 = stencil_chunks(nbx * nby, g.n[2], 8 / H);
+    const int kchunk = (g.n[2] + nchunk0 - 1) / nchunk0;
+    const int nchunk = (g.n[2] + kchunk - 1) / kchunk;
+    const dim3 grid(nbx, nby, nchunk), block(TX, H);
+    if (c.terms == FVK_TERMS_ALL)
+        k_jac_tiled<false, H><<<grid, block, 0, st>>>(g, c, span_aa, base, x, yv, yT, kchunk);
+    else
+        k_jac_tiled<true, H><<<grid, block, 0, st>>>(g, c, span_aa, base, x, yv, yT, kchunk);
 }
 
 void launch_jacvec(const Geo &g, Coefs c, int span_aa, int ext, const double *base,
                    const double *x, double *yv, double *yT, hipStream_t st) {
-    // tiles of the interior plane; k split into chunks so the grid fills the
-    // chip (>= ~2 blocks per CU) while each block keeps a long k-march
-    const int nbx = (g.n[0] + TX - 1) / TX, nby = (g.n[1] + TY - 1) / TY;
-    const int nchunk0 = stencil_chunks(nbx * nby, g.n[2]);
-    const int kchunk = (g.n[2] + nchunk0 - 1) / nchunk0;
-    const int nchunk = (g.n[2] + kchunk - 1) / kchunk;
-    const dim3 grid(nbx, nby, nchunk), block(TX, TY);
-    if (c.terms == FVK_TERMS_ALL)
-        k_jac_tiled<false><<<grid, block, 0, st>>>(g, c, span_aa && ext, base, x, yv, yT, kchunk);
+    // 64 x 8 tiles (one 512-thread block per CU, 10 halo rows staged per 8
+    // computed) once the grid is large enough to give every CU long marches;
+    // 64 x 4 tiles (two blocks per CU, 6 rows per 4) below that
+    const long cells = long(g.n[0]) * g.n[1] * g.n[2];
+    if (cells >= 200L * 200 * 200)
+        launch_jac_tiled<8>(g, c, span_aa && ext, base, x, yv, yT, st);
     else
-        k_jac_tiled<true><<<grid, block, 0, st>>>(g, c, span_aa && ext, base, x, yv, yT, kchunk);
+        launch_jac_tiled<4>(g, c, span_aa && ext, base, x, yv, yT, st);
 }
 
 void launch_residual(const Geo &g, Coefs c, int span_aa, const double *base, double *F,
@@ -1059,7 +1093,7 @@ void launch_jacvec_T(const Geo &g, Coefs c, int span_aa, int fold_ext, const dou
                      const double *yvel, const double *yT, double *x, hipStream_t st) {
     // tiles of the whole stored plane; k (all np2 planes) split into chunks
     const int nbx = (g.np[0] + TX - 1) / TX, nby = (g.np[1] + TY - 1) / TY;
-    const int nchunk0 = stencil_chunks(nbx * nby, g.np[2]);
+    const int nchunk0 = stencil_chunks(nbx * nby, g.np[2], 2);
     const int kchunk = (g.np[2] + nchunk0 - 1) / nchunk0;
     const int nchunk = (g.np[2] + kchunk - 1) / kchunk;
     const dim3 grid(nbx, nby, nchunk), block(TX, TY);

@@ -6,6 +6,7 @@ entry; bar: relative max-norm error <= 1e-10 (FP64 and mixed precision)."""
 import pytest
 import torch
 
+from oracle import ops
 from oracle.grid import TANH
 from tests.gpu_util import base, dev, krylov_input, rel_err, setup
 
@@ -89,3 +90,20 @@ def test_256cube_transpose_and_dot_product(fvk):
     lhs, rhs = ctx.dot(yd, Ax), ctx.dot(ATy, xd)
     scale = float(torch.linalg.norm(yd) * torch.linalg.norm(Ax))
     assert abs(lhs - rhs) < 1e-14 * scale
+
+
+@pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
+def test_large_ragged_grid_jacobian(fvk, bc):
+    """The forward Jacobian on a grid large enough for the 512-thread (64 x 8)
+    stencil tiles, ragged in x and y (the last tiles reach past the stored box,
+    whose halo then reads as zero), with all terms and with two coupling terms
+    switched off; every output entry against the oracle."""
+    print(f"case large ragged jacobian bc={bc}", flush=True)
+    g, orc, ctx = setup((208, 203, 197), TANH, 1.5, bc)
+    U = base(g, bc)
+    x = krylov_input(g, orc, 5000)
+    Ud, xd = dev(U), dev(x)
+    assert rel_err(ctx.fv_jacvec(Ud, xd), ops.jacvec(g, orc.prm, U, x)) < TOL
+    mask = ops.ALL_TERMS & ~(1 << (ops.TERM_U_GRAD_T + 2)) & ~(1 << ops.TERM_V_GRAD_U)
+    ctx.set_terms(mask)
+    assert rel_err(ctx.fv_jacvec(Ud, xd), ops.jacvec(g, orc.prm, U, x, mask)) < TOL
