@@ -151,7 +151,10 @@ fvk_status simple_forward(fvk_ctx *ctx, const double *vin, double *vout, double 
         const bool last_fixed = !sync && k + 1 >= fixed;
         const bool win = transposed && k == 0, wout = transposed && last_fixed;
         timing_begin(ctx, FVK_STAGE_CORRECT);
-        launch_correct_oop(g, src, dst, w.phi, p_out, w.div, w.red, st, win, wout);
+        // D v of the result is the next pass's right-hand side; after the last
+        // pass of a fixed count only its maximum (the block maxima) is needed
+        launch_correct_oop(g, src, dst, w.phi, p_out, last_fixed ? nullptr : w.div, w.red, st,
+                           win, wout);
         // the running record of asynchronous calls covers forward projections
         const bool record = last_fixed && !transposed;
         launch_max_reduce(w.red, correct_blocks(g), w.div_slots,

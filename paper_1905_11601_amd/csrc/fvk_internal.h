@@ -143,7 +143,7 @@ void launch_jacvec_T(const Geo &g, Coefs c, int span_aa, int fold_ext, const dou
 void launch_residual(const Geo &g, Coefs c, int span_aa, const double *base, double *F,
                      hipStream_t st);
 void launch_div(const Geo &g, const double *v, double *div, hipStream_t st, bool win = false);
-// v_out = v_in - G phi (wall entries 0), p_out += phi, div_out = D v_out,
+// v_out = v_in - G phi (wall entries 0), p_out += phi, div_out = D v_out (if non-null),
 // block maxima of |D v_out| to red[0 .. correct_blocks)
 void launch_correct_oop(const Geo &g, const double *vin, double *vout, const double *phi,
                         double *p_out, double *div_out, double *red, hipStream_t st,
