@@ -28,11 +28,19 @@ struct Blk {
     int x, y, z;
     long lin;   // logical linear index (unique per block)
 };
+// Logical index of hardware block b of nb: block b runs on XCD b % 8 as that
+// XCD's (b / 8)-th block; XCDs 0 .. r-1 (r = nb % 8) get q + 1 = nb / 8 + 1
+// consecutive logical indices, the others q -- a bijection for any nb.
+__device__ __forceinline__ long xcd_remap(long b, long nb) {
+    const long q = nb / 8, r = nb % 8, x = b % 8;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + b / 8;
+}
+
 __device__ __forceinline__ Blk xcd_block() {
     const int nbx = gridDim.x, nby = gridDim.y;
     const long nb = long(nbx) * nby * gridDim.z;
     const long b = (long(blockIdx.z) * nby + blockIdx.y) * nbx + blockIdx.x;
-    const long lb = (nb % 8) == 0 ? (b % 8) * (nb / 8) + b / 8 : b;
+    const long lb = xcd_remap(b, nb);
     Blk r;
     r.lin = lb;
     r.x = int(lb % nbx);
@@ -514,8 +522,7 @@ __global__ __launch_bounds__(TX *H, 8 / H) void k_jac_tiled(Geo g, Coefs c, int 
     const int nbx = gridDim.x, nby = gridDim.y, nbz = gridDim.z;
     const int nb = nbx * nby * nbz;
     const int b = (blockIdx.z * nby + blockIdx.y) * nbx + blockIdx.x;
-    int lb = b;
-    if ((nb % 8) == 0) lb = (b % 8) * (nb / 8) + b / 8;
+    const int lb = int(xcd_remap(b, nb));
     const int bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
     const int i0 = bx * TX, j0 = by * H;           // halo origin (interior starts at +1)
     const int i = i0 + 1 + tx, j = j0 + 1 + ty;
