@@ -1050,16 +1050,26 @@ int correct_blocks(const Geo &g) {
     return int(gr.x * gr.y * gr.z);
 }
 
-// k-chunks of the tiled stencils: marches of ~10 planes while that keeps the
-// grid at <= 2048 blocks, else 512 / tiles chunks (at least 2) -- measured on
-// 100^3, 160^3 and 256^3
-// k-chunks per tile column: marches of ~10 planes while the grid is small,
-// else just enough chunks for `per_cu` resident blocks on each of the 256 CUs
+// k-chunks per tile column.  The blocks run in rounds of 256 * per_cu
+// resident blocks, and a block marching P planes costs about P + 2 plane
+// steps (two planes staged before its first step); the chunk count minimises
+// rounds x (P + 2), ties going to more blocks.  A count that leaves a last
+// round nearly empty (e.g. 650 blocks on 512 slots) is what this avoids.
 static int stencil_chunks(int tiles, int nk, int per_cu) {
-    int nchunk = (nk + 9) / 10;
-    if (long(tiles) * nchunk > 1024L * per_cu)
-        nchunk = std::max(per_cu, 256 * per_cu / std::max(1, tiles));
-    return std::max(1, std::min(nchunk, nk));
+    const long slots = 256L * per_cu;
+    long best_cost = -1;
+    int best = 1;
+    for (int nc = 1; nc <= nk; ++nc) {
+        const int planes = (nk + nc - 1) / nc;
+        const int nc2 = (nk + planes - 1) / planes;   // chunks actually launched
+        const long rounds = (long(tiles) * nc2 + slots - 1) / slots;
+        const long cost = rounds * (planes + 2);
+        if (best_cost < 0 || cost < best_cost || (cost == best_cost && nc2 > best)) {
+            best_cost = cost;
+            best = nc2;
+        }
+    }
+    return best;
 }
 
 template <int H>
