@@ -7,6 +7,7 @@
 // other two extents as columns.  These are the only dense contractions of the
 // method and run on the matrix cores: v_mfma_f64_16x16x4f64 in FP64 mode,
 // v_mfma_f32_16x16x4f32 (FP32 inputs and accumulation) in mixed mode.
+#include <type_traits>
 #include <algorithm>
 
 #include "fvk_internal.h"
@@ -606,14 +607,23 @@ void launch_res(const Tc *M, const AxisView &v, const Tin *X, Tout *Y, const Tc 
     k_axis_res<Tc, Tin, Tout, XAX, SCALE, FWD, NW><<<nb, 64 * NW, 0, st>>>(M, v, X, Y, lR, l0, l1);
 }
 
-// 96 < ne <= 128 (the MFMA-bound sizes): register-resident factors; shorter
-// axes (latency-bound) and longer ones: the streaming kernel
+// 96 < ne <= 128 (the MFMA-bound sizes), and in FP64 also 64 < ne <= 96:
+// register-resident factors on a persistent grid (at 160 cells the streaming
+// kernel's 1,600 blocks leave a third round of resident blocks nearly empty:
+// 38.3 -> 34.5 us per FP64 transform; in FP32 the streaming kernel stays
+// faster there); shorter axes (latency-bound) and longer ones: the streaming
+// kernel
 template <typename Tc, typename Tin, typename Tout, bool XAX, bool SCALE, bool FWD>
 void run_half(const Tc *M, const AxisView &v, const Tin *X, Tout *Y, const Tc *lR,
               const Tc *l0, const Tc *l1, hipStream_t st) {
     const int ne = v.na - v.na / 2;
+    constexpr bool f64 = std::is_same<Tc, double>::value;
     if (ne > 96 && ne <= 128)
         launch_res<Tc, Tin, Tout, XAX, SCALE, FWD, 8>(M, v, X, Y, lR, l0, l1, st);
+    else if (f64 && ne > 80 && ne <= 96)
+        launch_res<Tc, Tin, Tout, XAX, SCALE, FWD, 6>(M, v, X, Y, lR, l0, l1, st);
+    else if (f64 && ne > 64 && ne <= 80)
+        launch_res<Tc, Tin, Tout, XAX, SCALE, FWD, 5>(M, v, X, Y, lR, l0, l1, st);
     else
         run_sym<Tc, Tin, Tout, XAX, SCALE, FWD>(M, v, X, Y, lR, l0, l1, st);
 }

@@ -14,7 +14,8 @@ TOL = 1e-10
 # smallest grid the library accepts (2 cells per axis), ragged and elongated
 # boxes (partial stencil tiles and transform tiles), several full tiles, and
 # axes that select each transform kernel variant: 150/130 cells (five waves per
-# block, fused z pair), 201 cells (register-resident factors, odd length)
+# block; FP64 register-resident factors), 201 cells (register-resident
+# factors, odd length)
 CASES = [((2, 2, 2), UNIFORM, 0.0), ((2, 3, 64), TANH, 1.5), ((6, 5, 7), TANH, 1.5),
          ((20, 20, 20), UNIFORM, 0.0), ((17, 33, 9), SINE, 0.12), ((40, 40, 40), TANH, 1.5),
          ((70, 67, 65), TANH, 1.5), ((150, 12, 130), TANH, 1.5), ((201, 6, 5), SINE, 0.1)]
