@@ -207,7 +207,7 @@ __global__ __launch_bounds__(BX *BY) void k_jac(Geo g, Coefs c, int span_aa,
 
 // ---------------------------------------------------------------- forward, tiled
 //
-// The Krylov-path Jacobian: 2.5D blocking.  A block owns a TX x TY tile of the
+// The Krylov-path Jacobian: 2.5D blocking.  A block owns a TX x H tile of the
 // interior (i, j) plane and marches in k over a chunk of planes; planes k-1,
 // k, k+1 of all eight input fields (x: u v w T, base: U V W Theta) with a
 // one-point halo in i and j sit in an LDS ring, so every global value is
@@ -226,8 +226,6 @@ struct Tile {
     static constexpr int TY = H, THP = H + 2, PLANE = TWP * THP, NT = TX * H,
                          PER = (PLANE + NT - 1) / NT;
 };
-// the transposed kernel's tile (64 x 4)
-constexpr int TY = 4, THP = TY + 2, PLANE = TWP * THP;
 
 // The thread's own column (offset 0 in i and j) at planes k-1, k, k+1 is
 // carried in registers along the k-march: each centre value is read from LDS
@@ -378,8 +376,6 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-constexpr int NT_T = TX * TY;
-constexpr int PER_T = (PLANE + NT_T - 1) / NT_T;   // plane entries per thread per field (64 x 4)
 
 // Plane-relative addressing for the k-march through buffer resources: the
 // descriptor of plane kk of a field (base, size in bytes) is block-uniform and
@@ -694,16 +690,18 @@ __device__ __forceinline__ double jt_temp(const AxT *T, const Coefs &c, const Ac
 // entries are staged already masked (momentum rows on interior faces, energy
 // rows on cells, folded) so the rows read them without tests.  The halo
 // origin is one point below the tile in x and y; planes -1 and nz+2 are zero.
-template <bool TERMS>
-__global__ __launch_bounds__(TX *TY, 2) void k_jacT_tiled(Geo g, Coefs c, int fold,
+template <bool TERMS, int H>
+__global__ __launch_bounds__(TX *H, 8 / H) void k_jacT_tiled(Geo g, Coefs c, int fold,
                                                           const double *__restrict__ base,
                                                           const double *__restrict__ yvel,
                                                           const double *__restrict__ yT,
                                                           double *__restrict__ x, int kchunk) {
+    using Tl = Tile<H>;
+    constexpr int PLANE = Tl::PLANE, NT_T = Tl::NT, PER_T = Tl::PER;
     __shared__ double lds[3][NF * PLANE];
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
     const Blk B = xcd_block();
-    const int i0 = B.x * TX - 1, j0 = B.y * TY - 1;   // halo origin
+    const int i0 = B.x * TX - 1, j0 = B.y * H - 1;    // halo origin
     const int i = i0 + 1 + tx, j = j0 + 1 + ty;
     const int np2 = g.np[2];
     const int kb = B.z * kchunk;
@@ -1106,20 +1104,29 @@ void launch_residual(const Geo &g, Coefs c, int span_aa, const double *base, dou
     k_jac<1><<<box_grid(g), dim3(BX, BY), 0, st>>>(g, c, 0, base, base, F, F + 3 * g.F);
 }
 
-void launch_jacvec_T(const Geo &g, Coefs c, int span_aa, int fold_ext, const double *base,
-                     const double *yvel, const double *yT, double *x, hipStream_t st) {
+template <int H>
+static void launch_jacT_tiled(const Geo &g, Coefs c, int fold, const double *base,
+                              const double *yvel, const double *yT, double *x, hipStream_t st) {
     // tiles of the whole stored plane; k (all np2 planes) split into chunks
-    const int nbx = (g.np[0] + TX - 1) / TX, nby = (g.np[1] + TY - 1) / TY;
-    const int nchunk0 = stencil_chunks(nbx * nby, g.np[2], 2);
+    const int nbx = (g.np[0] + TX - 1) / TX, nby = (g.np[1] + H - 1) / H;
+    const int nchunk0 = stencil_chunks(nbx * nby, g.np[2], 8 / H);
     const int kchunk = (g.np[2] + nchunk0 - 1) / nchunk0;
     const int nchunk = (g.np[2] + kchunk - 1) / kchunk;
-    const dim3 grid(nbx, nby, nchunk), block(TX, TY);
+    const dim3 grid(nbx, nby, nchunk), block(TX, H);
     if (c.terms == FVK_TERMS_ALL)
-        k_jacT_tiled<false><<<grid, block, 0, st>>>(g, c, fold_ext && span_aa, base, yvel, yT, x,
-                                                     kchunk);
+        k_jacT_tiled<false, H><<<grid, block, 0, st>>>(g, c, fold, base, yvel, yT, x, kchunk);
     else
-        k_jacT_tiled<true><<<grid, block, 0, st>>>(g, c, fold_ext && span_aa, base, yvel, yT, x,
-                                                    kchunk);
+        k_jacT_tiled<true, H><<<grid, block, 0, st>>>(g, c, fold, base, yvel, yT, x, kchunk);
+}
+
+void launch_jacvec_T(const Geo &g, Coefs c, int span_aa, int fold_ext, const double *base,
+                     const double *yvel, const double *yT, double *x, hipStream_t st) {
+    // tile heights as for the forward stencil
+    const long cells = long(g.n[0]) * g.n[1] * g.n[2];
+    if (cells >= 200L * 200 * 200)
+        launch_jacT_tiled<8>(g, c, fold_ext && span_aa, base, yvel, yT, x, st);
+    else
+        launch_jacT_tiled<4>(g, c, fold_ext && span_aa, base, yvel, yT, x, st);
 }
 
 void launch_div(const Geo &g, const double *v, double *div, hipStream_t st, bool win) {

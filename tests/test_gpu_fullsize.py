@@ -94,16 +94,22 @@ def test_256cube_transpose_and_dot_product(fvk):
 
 @pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
 def test_large_ragged_grid_jacobian(fvk, bc):
-    """The forward Jacobian on a grid large enough for the 512-thread (64 x 8)
-    stencil tiles, ragged in x and y (the last tiles reach past the stored box,
-    whose halo then reads as zero), with all terms and with two coupling terms
-    switched off; every output entry against the oracle."""
+    """The Jacobian on a grid large enough for the 512-thread (64 x 8) stencil
+    tiles, ragged in x and y (the last tiles reach past the stored box, whose
+    halo then reads as zero), with all terms and with two coupling terms
+    switched off; every output entry against the oracle.  The transposed
+    stencil (same tiles) on the insulated-wall case, which has the fold."""
     print(f"case large ragged jacobian bc={bc}", flush=True)
     g, orc, ctx = setup((208, 203, 197), TANH, 1.5, bc)
     U = base(g, bc)
     x = krylov_input(g, orc, 5000)
     Ud, xd = dev(U), dev(x)
     assert rel_err(ctx.fv_jacvec(Ud, xd), ops.jacvec(g, orc.prm, U, x)) < TOL
+    if bc == 1:
+        assert rel_err(ctx.fv_jacvec(Ud, xd, transpose=True), orc.jacvec_T(U, x)) < TOL
     mask = ops.ALL_TERMS & ~(1 << (ops.TERM_U_GRAD_T + 2)) & ~(1 << ops.TERM_V_GRAD_U)
     ctx.set_terms(mask)
     assert rel_err(ctx.fv_jacvec(Ud, xd), ops.jacvec(g, orc.prm, U, x, mask)) < TOL
+    if bc == 1:
+        orc.terms = mask
+        assert rel_err(ctx.fv_jacvec(Ud, xd, transpose=True), orc.jacvec_T(U, x)) < TOL
