@@ -392,6 +392,14 @@ bool run_sym_div(const Tc *M, const AxisView &v, const double *X, Tc *Y, const G
     const int ne = v.na - v.na / 2;
     const bool cp2 = (v.ncols + 31) / 32 >= 1024;
     const Tc *none = nullptr;
+    // long FP64 axes: four pencil tiles per block share each factor chunk
+    // (197 VGPRs, one block per CU as with two tiles): 188 instead of 195 us
+    // at 256^3; one tile per block (two blocks per CU) measured 250 us
+    if (std::is_same<Tc, double>::value && ne > 112 && (v.ncols + 63) / 64 >= 512) {
+        launch_sym<Tc, double, Tc, true, false, true, 8, 4, DIV>(M, v, X, Y, none, none, none, st,
+                                                                 dg);
+        return true;
+    }
 #define FVK_DIV_CASE(W)                                                                    \
     case W:                                                                                \
         if (cp2)                                                                           \
