@@ -388,6 +388,8 @@ __device__ __forceinline__ void lds_barrier() {
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef __amdgpu_buffer_rsrc_t Rsrc;
 constexpr unsigned kOutside = 0x80000000u;   // beyond any plane: reads as 0
+// s_waitcnt immediate (gfx9 encoding): vmcnt 0, expcnt and lgkmcnt not waited on
+constexpr int kVmcntZero = 0x0F70;
 
 __device__ __forceinline__ Rsrc plane_rsrc(const double *field, long plane_off, int bytes) {
     // dword 3 of a raw (untyped, stride 0) buffer descriptor on gfx9-family parts
@@ -541,6 +543,10 @@ __global__ __launch_bounds__(TX *H, 8 / H) void k_jac_tiled(Geo g, Coefs c, int 
     put_plane_rel<Tl>(lds[(kb - 1) % 3], tid, reg);
     fetch_plane_rel(g, fp, P, kb, tid, reg);
     put_plane_rel<Tl>(lds[kb % 3], tid, reg);
+    // every load so far has been consumed; saying so here keeps the compiler's
+    // wait analysis from carrying a stale pending load (a slot skipped on some
+    // lanes) into the k-loop, where its wait would also drain the prefetch
+    __builtin_amdgcn_s_waitcnt(kVmcntZero);
     fetch_plane_rel(g, fp, P, kb + 1, tid, reg);
     TileAcc<Tl::PLANE> X;
     X.c = (ty + 1) * TWP + tx + 1;
