@@ -29,6 +29,8 @@ def main(argv=None):
     ap.add_argument("--base", choices=("synthetic", "newton"), default="synthetic")
     ap.add_argument("--k", type=int, default=4, help="eigenvalues wanted")
     ap.add_argument("--m", type=int, default=100, help="Krylov dimension")
+    ap.add_argument("--keep", type=int, default=None,
+                    help="Ritz values kept at a restart (default (m + k) / 2)")
     ap.add_argument("--tol", type=float, default=1e-8, help="Ritz residual tolerance")
     ap.add_argument("--max-restarts", type=int, default=2000)
     ap.add_argument("--prec", choices=("fp64", "mixed"), default="fp64")
@@ -63,7 +65,7 @@ def main(argv=None):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     r = krylov_schur(ctx, base, k=args.k, m=args.m, v0=v0, tol=args.tol,
-                     max_restarts=args.max_restarts,
+                     max_restarts=args.max_restarts, keep=args.keep,
                      log=lambda s: log(s) if int(s.split()[1].rstrip(":")) % every == 0 else None)
     torch.cuda.synchronize()
     t_eig = time.perf_counter() - t1
@@ -71,7 +73,7 @@ def main(argv=None):
     out = {
         "grid": [args.n] * 3, "grid_kind": args.grid, "s": args.s, "span_bc": args.bc,
         "Gr": args.gr, "Pr": args.pr, "base": args.base, "precision": args.prec,
-        "k": args.k, "m": args.m, "tol": args.tol,
+        "k": args.k, "m": args.m, "keep": args.keep, "tol": args.tol,
         "converged": r.converged, "restarts": r.restarts, "krylov_vectors": r.nvec,
         "eigenvalues": [[float(np.real(v)), float(np.imag(v))] for v in r.lam],
         "ritz_residuals": res,
