@@ -38,6 +38,21 @@ def test_krylov_schur_matches_dense_pencil(fvk, bc, lagged):
         assert ritz_residual(ctx, dev(U), r.lam[q], r.X[q]) < 1e-9
 
 
+@pytest.mark.parametrize("keep", [10, 24])
+def test_krylov_schur_keep_option(fvk, keep):
+    """The restart keep count (fewer or more Ritz values than the default 18
+    for k = 6, m = 30) changes the path, not the converged eigenvalues."""
+    from paper_1905_11601_amd.eigs import krylov_schur
+    print(f"case eigs 5^3 keep={keep}", flush=True)
+    g, orc, ctx = setup((5, 5, 5), TANH, 1.5, 0)
+    U = base(g, 0)
+    lam_p = dense_pencil_eigs(g, orc.prm, U, 0)
+    v0 = dev(krylov_input(g, orc, 5000))
+    r = krylov_schur(ctx, dev(U), k=6, m=30, v0=v0, tol=1e-11, keep=keep, vectors=False)
+    assert r.converged
+    assert _match(r.lam, lam_p[:10], 6) < 1e-9
+
+
 @pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
 def test_krylov_schur_matches_arpack_on_oracle(fvk, bc):
     from paper_1905_11601_amd.eigs import krylov_schur
