@@ -33,7 +33,9 @@ def main(argv=None):
                     help="Ritz values kept at a restart (default (m + k) / 2)")
     ap.add_argument("--tol", type=float, default=1e-8, help="Ritz residual tolerance")
     ap.add_argument("--max-restarts", type=int, default=2000)
-    ap.add_argument("--prec", choices=("fp64", "mixed"), default="fp64")
+    ap.add_argument("--prec", choices=("fp64", "mixed", "both"), default="fp64",
+                    help="both: FP64, then mixed precision on the same base flow, with the "
+                         "eigenvalue differences")
     ap.add_argument("--seed", type=int, default=5000, help="seed of the start vector")
     args = ap.parse_args(argv)
 
@@ -58,29 +60,45 @@ def main(argv=None):
         steady_state(ctx, base, args.gr, log=log)
     t_base = time.perf_counter() - t0
     ctx.set_params(args.gr, args.pr)
-    if args.prec == "mixed":
-        ctx.set_precision(fvk.MIXED)
     v0 = ctx.project(torch.as_tensor(inputs.random_fields(ctx.n, args.seed)).cuda())
     every = max(1, args.max_restarts // 100)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    r = krylov_schur(ctx, base, k=args.k, m=args.m, v0=v0, tol=args.tol,
-                     max_restarts=args.max_restarts, keep=args.keep,
-                     log=lambda s: log(s) if int(s.split()[1].rstrip(":")) % every == 0 else None)
-    torch.cuda.synchronize()
-    t_eig = time.perf_counter() - t1
-    res = [ritz_residual(ctx, base, r.lam[q], r.X[q]) for q in range(len(r.lam))]
+
+    def solve(prec):
+        ctx.set_precision(fvk.MIXED if prec == "mixed" else fvk.FP64)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        r = krylov_schur(ctx, base, k=args.k, m=args.m, v0=v0, tol=args.tol,
+                         max_restarts=args.max_restarts, keep=args.keep,
+                         log=lambda s: log(s) if int(s.split()[1].rstrip(":")) % every == 0
+                         else None)
+        torch.cuda.synchronize()
+        t_eig = time.perf_counter() - t1
+        res = [ritz_residual(ctx, base, r.lam[q], r.X[q]) for q in range(len(r.lam))]
+        return {
+            "precision": prec, "converged": r.converged, "restarts": r.restarts,
+            "krylov_vectors": r.nvec,
+            "eigenvalues": [[float(np.real(v)), float(np.imag(v))] for v in r.lam],
+            "ritz_residuals": res, "eigen_seconds": t_eig}, r
+
     out = {
         "grid": [args.n] * 3, "grid_kind": args.grid, "s": args.s, "span_bc": args.bc,
-        "Gr": args.gr, "Pr": args.pr, "base": args.base, "precision": args.prec,
-        "k": args.k, "m": args.m, "keep": args.keep, "tol": args.tol,
-        "converged": r.converged, "restarts": r.restarts, "krylov_vectors": r.nvec,
-        "eigenvalues": [[float(np.real(v)), float(np.imag(v))] for v in r.lam],
-        "ritz_residuals": res,
-        "base_seconds": t_base, "eigen_seconds": t_eig,
+        "Gr": args.gr, "Pr": args.pr, "base": args.base, "k": args.k, "m": args.m,
+        "keep": args.keep, "tol": args.tol, "base_seconds": t_base,
     }
+    if args.prec == "both":
+        o64, r64 = solve("fp64")
+        o32, r32 = solve("mixed")
+        # each mixed-precision eigenvalue against the nearest FP64 one
+        d = [float(np.min(np.abs(r64.lam - l))) for l in r32.lam]
+        out.update({"fp64": o64, "mixed": o32, "mixed_vs_fp64_abs": d,
+                    "mixed_vs_fp64_max_rel": max(d) / float(np.abs(r64.lam).max())})
+        converged = r64.converged and r32.converged
+    else:
+        o, r = solve(args.prec)
+        out.update(o)
+        converged = r.converged
     print(json.dumps(out))
-    return 0 if r.converged else 1
+    return 0 if converged else 1
 
 
 if __name__ == "__main__":

@@ -247,6 +247,15 @@ def test_stability_driver_6cube(fvk, capsys):
     lam_p = dense_pencil_eigs(g, ops.Params(1e6, 0.71), U, 0)
     lam = np.array([complex(*v) for v in out["eigenvalues"]])
     assert _match(lam, lam_p[:6], 2) < 1e-9
+    # FP64 and mixed precision on the same base flow, with their differences
+    rc = stability.main(["--n", "6", "--k", "2", "--m", "24", "--tol", "1e-10",
+                         "--max-restarts", "400", "--prec", "both"])
+    out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert rc == 0 and out["fp64"]["converged"] and out["mixed"]["converged"]
+    assert out["mixed_vs_fp64_max_rel"] < 1e-6
+    for prec in ("fp64", "mixed"):
+        lam = np.array([complex(*v) for v in out[prec]["eigenvalues"]])
+        assert _match(lam, lam_p[:6], 2) < 1e-9
 
 
 def test_critical_grashof_6cube_term_switched(fvk):
