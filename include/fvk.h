@@ -71,6 +71,9 @@ typedef enum { FVK_FP64 = 0, FVK_MIXED = 1 } fvk_prec;
 fvk_status fvk_create(fvk_ctx **out, int nx, int ny, int nz, int grid_kind, double s,
                       int span_bc, double Gr, double Pr, int prec, void *hip_stream);
 fvk_status fvk_destroy(fvk_ctx *ctx);
+/* Later calls enqueue on hip_stream.  If asynchronous divergence records are
+ * pending (fvk_simple_stats), they are reduced on the old stream first and the
+ * old stream is synchronised. */
 fvk_status fvk_set_stream(fvk_ctx *ctx, void *hip_stream);
 /* Re-derive nu = Gr^-1/2, kappa = nu / Pr, b = 1 (eqs (1)-(2)). */
 fvk_status fvk_set_params(fvk_ctx *ctx, double Gr, double Pr);
@@ -154,7 +157,9 @@ fvk_status simple_krylov_vec(fvk_ctx *ctx, const double *base, const double *x, 
                              double *p_out, int transpose, int *passes, double *max_div);
 /* Largest max |D v| seen by asynchronous forward calls since the last query,
  * and the number of such calls that needed more passes than the fixed count.
- * Resets. */
+ * Resets.  The device keeps each asynchronous call's block maxima and reduces
+ * them 64 calls at a time; this call (and fvk_set_simple, fvk_set_stream)
+ * reduces the pending ones first. */
 fvk_status fvk_simple_stats(fvk_ctx *ctx, double *max_div, int *n_unconverged);
 
 /* One Arnoldi step on A (or A^T): V holds j+1 orthonormal 4-field vectors

@@ -69,6 +69,7 @@ void free_ws(fvk_ctx *ctx) {
     fr(w.vtmp2);
     fr(w.red);
     fr(w.dev_scalars);
+    fr(w.ring);
     fr(w.dev_counters);
     fr(w.div_slots);
     fr(w.coef_dev);
@@ -103,6 +104,16 @@ fvk_status write_coefs(fvk_ctx *ctx, const double *host, size_t count) {
                                hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     return FVK_OK;
+}
+
+// Reduce the pending asynchronous divergence records into the running maximum
+// and the count of calls above tolerance (stream-ordered after the calls).
+void flush_ring(fvk_ctx *ctx) {
+    Workspace &w = ctx->ws;
+    if (w.ring_n == 0) return;
+    launch_ring_reduce(w.ring, correct_blocks(ctx->geo), w.ring_n, w.div_slots + 1,
+                       w.dev_counters, ctx->simple_tol, ctx->stream);
+    w.ring_n = 0;
 }
 
 // ---- SIMPLE loop (Sec. 3.1, steps 1-3) ------------------------------------
@@ -152,14 +163,22 @@ fvk_status simple_forward(fvk_ctx *ctx, const double *vin, double *vout, double 
         const bool win = transposed && k == 0, wout = transposed && last_fixed;
         timing_begin(ctx, FVK_STAGE_CORRECT);
         // D v of the result is the next pass's right-hand side; after the last
-        // pass of a fixed count only its maximum (the block maxima) is needed
-        launch_correct_oop(g, src, dst, w.phi, p_out, last_fixed ? nullptr : w.div, w.red, st,
-                           win, wout);
-        // the running record of asynchronous calls covers forward projections
+        // pass of a fixed count only its maximum (the block maxima) is needed.
+        // The running record of asynchronous calls covers forward projections:
+        // their block maxima go to the next row of the ring, reduced kRing
+        // calls at a time (no reduction launch per call); other passes reduce
+        // at once
         const bool record = last_fixed && !transposed;
-        launch_max_reduce(w.red, correct_blocks(g), w.div_slots,
-                          record ? w.div_slots + 1 : nullptr, record ? w.dev_counters : nullptr,
-                          ctx->simple_tol, st);
+        if (record) {
+            launch_correct_oop(g, src, dst, w.phi, p_out, nullptr,
+                               w.ring + size_t(w.ring_n) * correct_blocks(g), st, win, wout);
+            if (++w.ring_n == kRing) flush_ring(ctx);
+        } else {
+            launch_correct_oop(g, src, dst, w.phi, p_out, last_fixed ? nullptr : w.div, w.red,
+                               st, win, wout);
+            launch_max_reduce(w.red, correct_blocks(g), w.div_slots, nullptr, nullptr,
+                              ctx->simple_tol, st);
+        }
         timing_end(ctx, FVK_STAGE_CORRECT);
         CHECK_LAUNCH(ctx);
         scaled_out = wout;
@@ -340,6 +359,7 @@ fvk_status fvk_create(fvk_ctx **out, int nx, int ny, int nz, int grid_kind, doub
                                                  multidot2_blocks(nvec(ctx)))) * 512);
     if ((st = dalloc(ctx, &w.red, w.red_len)) != FVK_OK) goto bad;
     if ((st = dalloc(ctx, &w.dev_scalars, 4096)) != FVK_OK) goto bad;
+    if ((st = dalloc(ctx, &w.ring, size_t(kRing) * correct_blocks(g))) != FVK_OK) goto bad;
     if ((st = dalloc(ctx, &w.dev_counters, 16)) != FVK_OK) goto bad;
     if ((st = dalloc(ctx, &w.div_slots, 4)) != FVK_OK) goto bad;
     w.coef_len = 65536;
@@ -428,6 +448,12 @@ fvk_status fvk_destroy(fvk_ctx *ctx) {
 
 fvk_status fvk_set_stream(fvk_ctx *ctx, void *s) {
     if (!ctx) return FVK_EINVAL;
+    if (ctx->ws.ring_n > 0) {
+        // the pending records are reduced on the old stream, which must be
+        // done before calls on the new one reuse the ring
+        flush_ring(ctx);
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    }
     ctx->stream = static_cast<hipStream_t>(s);
     return FVK_OK;
 }
@@ -476,6 +502,7 @@ fvk_status fvk_set_simple(fvk_ctx *ctx, double tol, int max_passes) {
     if (!ctx) return FVK_EINVAL;
     if (!(tol > 0) || max_passes < 1 || max_passes > 100)
         return fail(ctx, FVK_EINVAL, "bad SIMPLE settings");
+    flush_ring(ctx);   // the pending records are tested against the old tolerance
     ctx->simple_tol = tol;
     ctx->simple_cap = max_passes;
     return FVK_OK;
@@ -601,6 +628,8 @@ fvk_status simple_krylov_vec(fvk_ctx *ctx, const double *base, const double *x, 
 
 fvk_status fvk_simple_stats(fvk_ctx *ctx, double *max_div, int *n_unconverged) {
     if (!ctx) return FVK_EINVAL;
+    flush_ring(ctx);
+    CHECK_LAUNCH(ctx);
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     double m = 0.0;
     int cnt = 0;

@@ -92,6 +92,11 @@ struct Workspace {
     double *red = nullptr;          // reduction scratch (partials)
     size_t red_len = 0;
     double *dev_scalars = nullptr;  // small device scalars (dot products, norms)
+    // block maxima of |D v| of the last pass of asynchronous forward calls,
+    // one row of correct_blocks per call, reduced kRing rows at a time (or when
+    // the record is read, the stream or the tolerance changes)
+    double *ring = nullptr;
+    int ring_n = 0;
     int *dev_counters = nullptr;    // [0] async calls above tolerance, [1] block counter
     double *div_slots = nullptr;    // [0] max |D v| of the last pass, [1] running max (async)
     double *host_pinned = nullptr;  // pinned host staging for small reads
@@ -149,6 +154,12 @@ void launch_correct_oop(const Geo &g, const double *vin, double *vout, const dou
                         double *p_out, double *div_out, double *red, hipStream_t st,
                         bool win = false, bool wout = false);
 int correct_blocks(const Geo &g);
+// rows of the ring of asynchronous divergence records
+constexpr int kRing = 64;
+// for each of the n rows of nblk block maxima (in order): running[0] =
+// max(running[0], row max), count_over[0] += (row max >= tol)
+void launch_ring_reduce(const double *rows, int nblk, int n, double *running, int *count_over,
+                        double tol, hipStream_t st);
 // interior velocity faces scaled by W = d_A h_B h_C (inverse: by 1/W), rest 0
 void launch_face_scale(const Geo &g, const double *src, double *dst, int inverse,
                        hipStream_t st);

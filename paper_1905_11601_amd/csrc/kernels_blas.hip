@@ -232,6 +232,35 @@ __global__ __launch_bounds__(NTR) void k_max_reduce(const double *__restrict__ p
     }
 }
 
+// the asynchronous divergence records: row e holds the block maxima of one
+// call; one block reduces the rows in call order
+__global__ __launch_bounds__(NTR) void k_ring_reduce(const double *__restrict__ rows, int nblk,
+                                                     int n, double *running, int *count_over,
+                                                     double tol) {
+    __shared__ double sh[NTR / 64];
+    double run = 0.0;
+    int cnt = 0;
+    for (int e = 0; e < n; ++e) {
+        const double *r = rows + long(e) * nblk;
+        double v = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += NTR) v = fmax(v, r[b]);
+        for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int k = 0; k < NTR / 64; ++k) t = fmax(t, sh[k]);
+            run = fmax(run, t);
+            if (!(t < tol)) ++cnt;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        running[0] = fmax(running[0], run);
+        count_over[0] += cnt;
+    }
+}
+
 // partials[blk] = max |x| over the block's rows
 __global__ __launch_bounds__(NT) void k_absmax(const double *__restrict__ x, size_t n,
                                                size_t chunk, double *__restrict__ partials) {
@@ -340,6 +369,11 @@ void launch_basis_rotate(double *V, size_t ldv, int m, const double *Q_dev, int 
 void launch_max_reduce(const double *partials, int nblk, double *out, double *running,
                        int *count_over, double tol, hipStream_t st) {
     k_max_reduce<<<1, NTR, 0, st>>>(partials, nblk, out, running, count_over, tol);
+}
+
+void launch_ring_reduce(const double *rows, int nblk, int n, double *running, int *count_over,
+                        double tol, hipStream_t st) {
+    k_ring_reduce<<<1, NTR, 0, st>>>(rows, nblk, n, running, count_over, tol);
 }
 
 void launch_absmax(const double *x, size_t n, double *partials, int nblk, hipStream_t st) {

@@ -87,6 +87,31 @@ def test_asynchronous_calls_record_divergence(fvk):
     assert rel_err(y, orc.krylov_vec(base(g, 0), krylov_input(g, orc, 2002))) < TOL
 
 
+def test_asynchronous_records_across_ring_flushes(fvk):
+    """The records of asynchronous calls are reduced 64 calls at a time: 150
+    calls (two full flushes, 22 pending at the query) all count, the maximum
+    is that of the calls, and a tolerance change reduces the pending records
+    against the old tolerance first."""
+    g, orc, ctx = setup((12, 12, 12), TANH, 1.5, 0)
+    U = dev(base(g, 0))
+    x = dev(krylov_input(g, orc, 2002))
+    _, _, dref = ctx.simple_krylov_vec(U, x, info=True)   # the same call, synchronous
+    ctx.simple_stats()
+    y = ctx.empty()
+    ctx.set_simple(1e-30, 10)   # every call is then above tolerance
+    for _ in range(150):
+        ctx.simple_krylov_vec(U, x, out=y)
+    dmax, nbad = ctx.simple_stats()
+    assert nbad == 150 and dmax == dref
+    for _ in range(10):
+        ctx.simple_krylov_vec(U, x, out=y)
+    ctx.set_simple(1.0, 10)     # the 10 pending records count against 1e-30
+    for _ in range(10):
+        ctx.simple_krylov_vec(U, x, out=y)
+    dmax, nbad = ctx.simple_stats()
+    assert nbad == 10 and dmax == dref
+
+
 @pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
 def test_mixed_precision_krylov_vec(fvk, bc):
     g, orc, ctx = setup((24, 20, 28), TANH, 1.5, bc, prec=1)
