@@ -315,6 +315,24 @@ __global__ __launch_bounds__(64 * NW) void k_axis_sym(const Tc *__restrict__ M, 
         ae[cp] = acc_t{0, 0, 0, 0};
         ao[cp] = acc_t{0, 0, 0, 0};
     }
+    // SCALE: the eigenvalue sums of this lane's outputs, loaded before the K
+    // loop (clamped indices) so the epilogue does not wait on a gather
+    constexpr int NS = SCALE ? CP : 1;
+    Tc s01[NS][4], sre[NS][4], sro[NS][4];
+    if (SCALE) {
+#pragma unroll
+        for (int cp = 0; cp < NS; ++cp)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int t = min(wv * 16 + (XAX ? lr : Mfma<Tc>::row(lane, r)), ne - 1);
+                const int pp = min(p0 + cp * 16 + (XAX ? Mfma<Tc>::row(lane, r) : lr),
+                                   v.ncols - 1);
+                const int ph = col_hi(v, pp);
+                s01[cp][r] = lam0[pp - ph * v.n0] + lam1[ph];
+                sre[cp][r] = lamR[t];
+                sro[cp][r] = lamR[min(ne + t, n - 1)];
+            }
+    }
     fetch(0);
     put(0, 0);
     lds_barrier();
@@ -357,10 +375,9 @@ __global__ __launch_bounds__(64 * NW) void k_axis_sym(const Tc *__restrict__ M, 
             if (FWD) {
                 Tc ve = pe, vo = po;
                 if (SCALE) {
-                    const int ph = col_hi(v, pp);
-                    const Tc l01 = lam0[pp - ph * v.n0] + lam1[ph];
-                    ve = (t == 0 && pp == 0) ? Tc(0) : pe * recip(lamR[t] + l01);
-                    if (t < no) vo = po * recip(lamR[ne + t] + l01);
+                    const Tc l01 = s01[SCALE ? cp : 0][r];
+                    ve = (t == 0 && pp == 0) ? Tc(0) : pe * recip(sre[SCALE ? cp : 0][r] + l01);
+                    if (t < no) vo = po * recip(sro[SCALE ? cp : 0][r] + l01);
                 }
                 Y[base + long(t) * v.sb] = Tout(ve);
                 if (t < no) Y[base + long(ne + t) * v.sb] = Tout(vo);
