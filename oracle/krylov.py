@@ -10,6 +10,10 @@
                       A x = [P_div(J x)_v, Ext_T (J x)_T]
                       -- pinned by the dense saddle-point pencil at 4^3-6^3
                          (oracle.dense), range(A) in the constraint subspace S.
+                      With ``shift`` sigma: P (J + sigma I) x = (A + sigma P) x,
+                      the operator of the eigenvalue iteration on stable
+                      states -- pinned by the same dense pencil (its spectrum
+                      is the pencil's shifted by sigma plus 0 on ker P).
 * ``krylov_vec_T``    A^T y in the Euclidean inner product of the stored
                       arrays, computed by reverse-mode differentiation of the
                       forward definition (a library primitive) with the single
@@ -98,17 +102,24 @@ class Oracle:
         return g.detach()
 
     # ---- the Krylov operator -----------------------------------------------
-    def krylov_vec(self, base, x, passes=None, with_info=False):
+    def krylov_vec(self, base, x, passes=None, with_info=False, shift=0.0):
+        """A x = [P_div (J x)_v, Ext_T (J x)_T] (eqs (11)-(13)).  With a shift
+        sigma the raw right-hand side is (J + sigma I) x, i.e. the operator
+        P (J + sigma I) = A + sigma P: on the constraint subspace S it is
+        A + sigma, on ker P it is P J (eigenvalue 0) -- the eigenvalues of
+        eq. (10) move right by sigma while the complement of S stays at 0."""
         Jx = ops.jacvec(self.grid, self.prm, base, x, self.terms)
+        if shift:
+            Jx = Jx + shift * x
         v, p, k, dmax = self.simple_project([Jx[0], Jx[1], Jx[2]], passes)
         y = torch.stack(v + [ext_T(self.grid, Jx[3], self.bc)])
         if with_info:
             return y, p, k, dmax
         return y
 
-    def krylov_vec_T(self, base, y):
+    def krylov_vec_T(self, base, y, shift=0.0):
         x = torch.zeros(self.shape4, dtype=DT, requires_grad=True)
-        Ax = self.krylov_vec(base, x, passes=1)
+        Ax = self.krylov_vec(base, x, passes=1, shift=shift)
         (g,) = torch.autograd.grad(Ax, x, grad_outputs=y.to(DT))
         return g.detach()
 

@@ -106,6 +106,34 @@ def test_krylov_operator_eigs_match_dense_pencil(bc):
     assert np.max(np.abs(PA - A[:, ::7])) < 1e-12 * np.max(np.abs(A))
 
 
+@pytest.mark.parametrize("bc", [CC, AA])
+def test_shifted_operator_spectrum_is_shifted_pencil_plus_null(bc):
+    """P (J + sigma I) = A + sigma P: its spectrum is that of eq. (10) (the
+    finite eigenvalues of the saddle-point pencil, no TPF or SIMPLE code)
+    moved right by sigma, plus the eigenvalue 0 of the complement ker P, whose
+    dimension is that of the stored arrays minus that of S (the pencil's
+    eigenvalue count); the transpose is the dense transpose."""
+    g = Grid(4, 3, 4, kind=TANH, s=1.5)
+    prm = ops.Params(1e6, 0.71)
+    base = base_flow(g, bc)
+    orc = Oracle(g, prm, bc)
+    lam_p = dense_pencil_eigs(g, prm, base, bc)
+    sigma = 2.75
+    n = 4 * int(np.prod(g.shape))
+    As = dense_matrix(lambda e: orc.krylov_vec(base, e, shift=sigma), n, (4,) + g.shape)
+    lam = np.linalg.eigvals(As)
+    scale = np.abs(lam).max()
+    null = np.abs(lam) < 1e-9 * scale
+    assert int(null.sum()) == n - len(lam_p)
+    from oracle.krylov import eig_order
+    phys = lam[~null] - sigma
+    phys = phys[eig_order(phys)]
+    assert len(phys) == len(lam_p)
+    assert np.max(np.abs(phys - lam_p)) < 1e-9 * np.max(np.abs(lam_p))
+    AsT = dense_matrix(lambda e: orc.krylov_vec_T(base, e, shift=sigma), n, (4,) + g.shape)
+    assert np.max(np.abs(AsT - As.T)) < 1e-12 * np.max(np.abs(As))
+
+
 def test_transpose_equals_dense_transpose():
     g = Grid(3, 3, 2, kind=TANH, s=1.5)
     prm = ops.Params(1e5, 0.71)
