@@ -71,9 +71,10 @@ typedef enum { FVK_FP64 = 0, FVK_MIXED = 1 } fvk_prec;
 fvk_status fvk_create(fvk_ctx **out, int nx, int ny, int nz, int grid_kind, double s,
                       int span_bc, double Gr, double Pr, int prec, void *hip_stream);
 fvk_status fvk_destroy(fvk_ctx *ctx);
-/* Later calls enqueue on hip_stream.  If asynchronous divergence records are
- * pending (fvk_simple_stats), they are reduced on the old stream first and the
- * old stream is synchronised. */
+/* Later calls enqueue on hip_stream.  All calls share the context's
+ * workspace, so the old stream is synchronised first (after reducing any
+ * pending asynchronous divergence records, fvk_simple_stats, on it): a call
+ * on the new stream never overlaps work still queued on the old one. */
 fvk_status fvk_set_stream(fvk_ctx *ctx, void *hip_stream);
 /* Re-derive nu = Gr^-1/2, kappa = nu / Pr, b = 1 (eqs (1)-(2)). */
 fvk_status fvk_set_params(fvk_ctx *ctx, double Gr, double Pr);
@@ -101,6 +102,26 @@ enum {
     FVK_TERMS_ALL = (1 << 9) - 1
 };
 fvk_status fvk_set_terms(fvk_ctx *ctx, int mask);
+/* Spectral shift of the Krylov operator for the eigenvalue problem of
+ * eq. (10) (Sec. 3.1: rightmost eigenvalues by Arnoldi).  A = P J maps every
+ * stored array into the constraint subspace S (divergence-free velocity,
+ * homogeneous boundary values), so on whole arrays it has, besides the
+ * spectrum of eq. (10) on S, the eigenvalue 0 with the multiplicity of the
+ * complement ker P.  With sigma != 0, simple_krylov_vec (and arnoldi_step,
+ * arnoldi_step_lagged, everything built on them) applies
+ *     A_sigma = P (J + sigma I) = A + sigma P         (transpose = 0)
+ *     A_sigma^T = J^T P^T + sigma P^T                 (transpose = 1)
+ * whose spectrum is {lambda + sigma : lambda of eq. (10)} together with the
+ * 0 of ker P: the Krylov spaces, Ritz vectors and residuals are those of
+ * A - sigma (I - P), which moves the complement to -sigma, and the physical
+ * eigenvalues are the Ritz values minus sigma.  The stencils add sigma times
+ * the centre value they already hold: no extra memory traffic.  p_out then
+ * accumulates the pressure of P (J + sigma I) x.  fv_jacvec, fvk_project,
+ * fv_residual, fvk_linear_solve and newton_step are never shifted (the
+ * linear solves switch it off for the duration of the call).  Default 0.
+ * Returns FVK_EINVAL for a non-finite sigma. */
+fvk_status fvk_set_shift(fvk_ctx *ctx, double sigma);
+fvk_status fvk_get_shift(const fvk_ctx *ctx, double *sigma);
 fvk_status fvk_set_precision(fvk_ctx *ctx, int prec);
 /* SIMPLE loop control (Sec. 3.1): stop when max |D v| < tol (default 1e-9,
  * the paper's pointwise criterion), at most max_passes passes (default 10). */

@@ -61,6 +61,7 @@ class Ctx:
         self.span_bc, self.grid_kind, self.s = span_bc, grid, s
         self.Gr, self.Pr, self.prec = Gr, Pr, prec
         self.terms = TERMS_ALL
+        self.shift = 0.0
         F = ctypes.c_size_t()
         N = ctypes.c_size_t()
         self.lib.fvk_layout(h, None, ctypes.byref(F), ctypes.byref(N))
@@ -108,6 +109,12 @@ class Ctx:
         """Coupling terms kept in the linearised operator (TERM_* bits)."""
         self._check(self.lib.fvk_set_terms(self.h, int(mask)))
         self.terms = int(mask)
+
+    def set_shift(self, sigma):
+        """Krylov operator A + sigma P in simple_krylov_vec / arnoldi_step
+        (fvk_set_shift); 0 restores A."""
+        self._check(self.lib.fvk_set_shift(self.h, float(sigma)))
+        self.shift = float(sigma)
 
     def set_precision(self, prec):
         self._check(self.lib.fvk_set_precision(self.h, prec))

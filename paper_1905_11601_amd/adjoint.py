@@ -64,9 +64,17 @@ def dlam_dGr(ctx, base, x, y, dAx=None):
 
 
 def left_eigvecs(ctx, base, lam, k, m, seed_vec, tol=1e-10, max_restarts=200):
-    """Eigenvectors of A^T for the conjugates of the eigenvalues ``lam``
-    (rightmost k of A^T).  seed_vec: any real CUDA vector; the start vector is
-    A^T seed_vec so the Krylov space lies in the range of A^T."""
+    """Left eigenvectors for the eigenvalues ``lam``: eigenvectors of the
+    transposed Krylov operator for the conjugates (rightmost k).  seed_vec:
+    any real CUDA vector; the start vector is A^T seed_vec so the Krylov
+    space lies in the range of A^T.
+
+    The solve runs on the shifted operator (A + sigma P)^T (krylov_schur's
+    default, r.shift = sigma).  Its left eigenvectors agree with those of A
+    on the constraint subspace S, and differ only on the complement ker P (by
+    the factor lambda / (lambda + sigma) there).  Eigenvalue derivatives
+    y^H A' x / y^H x with x in S see only the former, so they are those of A;
+    a left eigenvector of A itself, where needed, is A^T y / conj(lambda)."""
     from .eigs import krylov_schur
     v0 = ctx.simple_krylov_vec(base, seed_vec.reshape(ctx.shape4), transpose=True)
     r = krylov_schur(ctx, base, k, m, v0, tol=tol, max_restarts=max_restarts, transpose=True)

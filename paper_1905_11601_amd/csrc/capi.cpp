@@ -448,13 +448,27 @@ fvk_status fvk_destroy(fvk_ctx *ctx) {
 
 fvk_status fvk_set_stream(fvk_ctx *ctx, void *s) {
     if (!ctx) return FVK_EINVAL;
-    if (ctx->ws.ring_n > 0) {
-        // the pending records are reduced on the old stream, which must be
-        // done before calls on the new one reuse the ring
-        flush_ring(ctx);
-        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    }
+    // every call shares the context's workspace (scratch vectors, Poisson
+    // arrays, reduction slots, the record ring): work still queued on the old
+    // stream must finish before calls on the new one reuse it; the pending
+    // divergence records are reduced on the old stream first
+    flush_ring(ctx);
+    CHECK_LAUNCH(ctx);
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
     ctx->stream = static_cast<hipStream_t>(s);
+    return FVK_OK;
+}
+
+fvk_status fvk_set_shift(fvk_ctx *ctx, double sigma) {
+    if (!ctx) return FVK_EINVAL;
+    if (!std::isfinite(sigma)) return fail(ctx, FVK_EINVAL, "shift must be finite");
+    ctx->shift = sigma;
+    return FVK_OK;
+}
+
+fvk_status fvk_get_shift(const fvk_ctx *ctx, double *sigma) {
+    if (!ctx || !sigma) return FVK_EINVAL;
+    *sigma = ctx->shift;
     return FVK_OK;
 }
 
@@ -599,9 +613,12 @@ fvk_status simple_krylov_vec(fvk_ctx *ctx, const double *base, const double *x, 
     const long F = g.F;
     const int aa = ctx->bc == FVK_SPAN_AA;
     if (!transpose) {
-        // momentum predictor + temperature RHS (eqs (11)-(12)), T part final
+        // momentum predictor + temperature RHS (eqs (11)-(12)), T part final;
+        // with a shift the stencil returns (J + shift I) x
+        Coefs cs = ctx->co;
+        cs.sigma = ctx->shift;
         timing_begin(ctx, FVK_STAGE_JACVEC);
-        launch_jacvec(g, ctx->co, aa, 1, base, x, w.vtmp, y + 3 * F, st);
+        launch_jacvec(g, cs, aa, 1, base, x, w.vtmp, y + 3 * F, st);
         timing_end(ctx, FVK_STAGE_JACVEC);
         CHECK_LAUNCH(ctx);
         const bool sync = passes || max_div;
@@ -619,8 +636,10 @@ fvk_status simple_krylov_vec(fvk_ctx *ctx, const double *base, const double *x, 
     if (passes) *passes = k;
     if (max_div) *max_div = dmax;
     if (s != FVK_OK) return s;
+    Coefs cs = ctx->co;
+    cs.sigma = ctx->shift;
     timing_begin(ctx, FVK_STAGE_JACVEC);
-    launch_jacvec_T(g, ctx->co, aa, 1, base, w.vtmp, x + 3 * F, y, st);
+    launch_jacvec_T(g, cs, aa, 1, base, w.vtmp, x + 3 * F, y, st);
     timing_end(ctx, FVK_STAGE_JACVEC);
     CHECK_LAUNCH(ctx);
     return FVK_OK;

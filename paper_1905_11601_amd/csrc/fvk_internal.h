@@ -38,6 +38,10 @@ struct Coefs {
     // axis U_a dT/dx_a and v_a dTheta/dx_a; `terms` is the bit mask
     double fb = 1.0, fuv = 1.0, fvu = 1.0, fut[3] = {1.0, 1.0, 1.0}, fvt[3] = {1.0, 1.0, 1.0};
     int terms = FVK_TERMS_ALL;
+    // spectral shift of the Krylov operator (fvk_set_shift): the Jacobian
+    // stencils of simple_krylov_vec return (J + sigma I) x, so the Krylov
+    // vector becomes P (J + sigma I) x = (A + sigma P) x; 0 elsewhere
+    double sigma = 0.0;
 };
 
 // Host-side description of one axis (natural indexing, see fvk.h).
@@ -117,6 +121,7 @@ struct fvk_ctx {
     double simple_tol = 1e-9;
     int simple_cap = 10;
     int mixed_passes = 2;           // fixed pass count of asynchronous mixed calls
+    double shift = 0.0;             // fvk_set_shift: Krylov operator A + shift P
     fvk::AxisHost ax[3];
     fvk::Eig1D eig[3];
     fvk::EigSym esym[3];

@@ -564,10 +564,15 @@ __global__ __launch_bounds__(TX *H, 8 / H) void k_jac_tiled(Geo g, Coefs c, int 
             X.s[1] = lds[k % 3];
             X.s[2] = lds[(k + 1) % 3];
             X.read_centres();
-            const double u = (i <= nx - 1) ? jrow_mom<0, TERMS>(C, X, c) : 0.0;
-            const double v = (j <= ny - 1) ? jrow_mom<1, TERMS>(C, X, c) : 0.0;
-            const double w = (k <= nz - 1) ? jrow_mom<2, TERMS>(C, X, c) : 0.0;
-            const double t = jrow_energy<TERMS>(C, X, c);
+            // rows of (J + sigma I) x (sigma = 0 outside the shifted Krylov
+            // operator); the centre values are already in registers
+            const double u = (i <= nx - 1) ? jrow_mom<0, TERMS>(C, X, c) + c.sigma * X.cen[1][0]
+                                           : 0.0;
+            const double v = (j <= ny - 1) ? jrow_mom<1, TERMS>(C, X, c) + c.sigma * X.cen[1][1]
+                                           : 0.0;
+            const double w = (k <= nz - 1) ? jrow_mom<2, TERMS>(C, X, c) + c.sigma * X.cen[1][2]
+                                           : 0.0;
+            const double t = jrow_energy<TERMS>(C, X, c) + c.sigma * X.cen[1][3];
             const long pk = long(k) * g.s[2];
             const Rsrc r4[4] = {plane_rsrc(yv, pk, pbytes), plane_rsrc(yv + F, pk, pbytes),
                                 plane_rsrc(yv + 2 * F, pk, pbytes), plane_rsrc(yT, pk, pbytes)};
@@ -784,10 +789,11 @@ __global__ __launch_bounds__(TX *H, 8 / H) void k_jacT_tiled(Geo g, Coefs c, int
             X.read_centres();
             T[2] = axt(g.ax[2], k);
             const long p = pos(g, i, j, k);
-            x[p] = jt_vel<0, TERMS>(T, c, X);
-            x[p + F] = jt_vel<1, TERMS>(T, c, X);
-            x[p + 2 * F] = jt_vel<2, TERMS>(T, c, X);
-            x[p + 3 * F] = jt_temp<TERMS>(T, c, X);
+            // (J + sigma I)^T z with z the staged (masked, folded) input
+            x[p] = jt_vel<0, TERMS>(T, c, X) + c.sigma * X.cen[1][0];
+            x[p + F] = jt_vel<1, TERMS>(T, c, X) + c.sigma * X.cen[1][1];
+            x[p + 2 * F] = jt_vel<2, TERMS>(T, c, X) + c.sigma * X.cen[1][2];
+            x[p + 3 * F] = jt_temp<TERMS>(T, c, X) + c.sigma * X.cen[1][3];
             X.shift();
         }
         lds_barrier();

@@ -199,24 +199,49 @@ fvk_status bicgstab2(Dev &d, const double *base, const double *b, double *x, dou
     d.copy(xbest, x);
     d.copy(xstart, x);
     *its = 0;
+    // a breakdown of the BiCG recurrences (rho, gamma or omega zero or not
+    // finite) restarts them from the true residual with a fresh shadow
+    // residual; two breakdowns in a row end the iteration
+    int breakdowns = 0;
     while (res > tol && *its < max_it && d.st == FVK_OK) {
         rho0 = -omega * rho0;
-        for (int j = 0; j < L; ++j) {
+        bool broke = !(std::isfinite(rho0) && rho0 != 0.0);
+        for (int j = 0; j < L && !broke; ++j) {
             const double rho1 = d.dot(r[j], r0t);
-            if (rho0 == 0.0) break;
             const double beta = alpha * rho1 / rho0;
             rho0 = rho1;
             for (int i = 0; i <= j; ++i) d.axpby(u[i], 1.0, r[i], -beta);   // u_i = r_i - beta u_i
             d.apply(base, u[j], u[j + 1]);
             ++*nvec;
             const double gamma = d.dot(u[j + 1], r0t);
-            if (gamma == 0.0) break;
+            if (!(std::isfinite(gamma) && gamma != 0.0 && std::isfinite(beta))) {
+                broke = true;
+                break;
+            }
             alpha = rho0 / gamma;
             for (int i = 0; i <= j; ++i) d.axpby(r[i], -alpha, u[i + 1], 1.0);
             d.apply(base, r[j], r[j + 1]);
             ++*nvec;
             d.axpby(x, alpha, u[0], 1.0);
         }
+        if (broke) {
+            if (++breakdowns >= 2 || d.st != FVK_OK) break;
+            if (verbose())
+                std::fprintf(stderr, "[fvk] bicgstab(2) breakdown at it %d: restart\n", *its);
+            if (best < res) d.copy(x, xbest);
+            d.apply(base, x, tmp);
+            ++*nvec;
+            d.copy(r[0], b);
+            d.axpby(r[0], -1.0, tmp, 1.0);
+            d.copy(r0t, r[0]);
+            d.fill(u[0], 0.0);
+            rho0 = 1.0;
+            alpha = 0.0;
+            omega = 1.0;
+            res = d.nrm(r[0]) / bn;
+            continue;
+        }
+        breakdowns = 0;
         // minimal-residual part (modified Gram-Schmidt on r_1..r_L)
         double tau[L + 1][L + 1] = {}, sig[L + 1] = {}, gp[L + 1] = {}, g[L + 1] = {},
                g2[L + 1] = {};
@@ -306,6 +331,16 @@ void fvk_newton_defaults(fvk_newton_opts *o) {
 
 namespace {
 
+// The linear solves of the Newton iteration are on A itself: the spectral
+// shift of fvk_set_shift (an eigenvalue-solver setting) is switched off for
+// the duration of a call and restored afterwards.
+struct NoShift {
+    fvk_ctx *ctx;
+    double saved;
+    explicit NoShift(fvk_ctx *c) : ctx(c), saved(c->shift) { c->shift = 0.0; }
+    ~NoShift() { ctx->shift = saved; }
+};
+
 // GMRES(m) then BiCGstab(2) on A x = b; V: (m+1) vectors, work: 10 vectors.
 fvk_status linear_solve(Dev &d, const double *base, const double *b, double *x, double *V,
                         double *work, const fvk_newton_opts &o, fvk_newton_report &R) {
@@ -337,6 +372,7 @@ fvk_status fvk_linear_solve(fvk_ctx *ctx, const double *base, const double *b, d
     fvk_newton_defaults(&o);
     if (opts) o = *opts;
     if (o.gmres_m < 1 || o.gmres_m > 400) return FVK_EINVAL;
+    const NoShift unshifted(ctx);
     fvk_newton_report R;
     std::memset(&R, 0, sizeof(R));
     size_t ntot = 0;
@@ -367,6 +403,7 @@ fvk_status newton_step(fvk_ctx *ctx, double *base, const fvk_newton_opts *opts,
     fvk_newton_defaults(&o);
     if (opts) o = *opts;
     if (o.gmres_m < 1 || o.gmres_m > 400 || o.max_newton < 0) return FVK_EINVAL;
+    const NoShift unshifted(ctx);
     fvk_newton_report R;
     std::memset(&R, 0, sizeof(R));
     size_t ntot = 0;

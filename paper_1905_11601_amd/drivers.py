@@ -104,11 +104,10 @@ def critical_gr(ctx, base, Gr0, v0, seed, k=4, m=40, tol=1e-10, gr_rtol=1e-7, ma
     mechanism experiment of Sec. 4.2); the steady states and U' always use
     the full equations.
 
-    Where a real eigenvalue crosses zero it meets, near the crossing, the null
-    cluster of the stored-array operator (eigenvalue 0 on the complement of
-    the constraint subspace, purged by krylov_schur): its attainable accuracy
-    is then ~1e-8 and gr_rtol should not be set below the corresponding
-    relative change of Gr.  Oscillatory crossings are not affected."""
+    The eigenvalue solves run on the shifted operator A + sigma P
+    (krylov_schur's default), so a real eigenvalue crossing zero stays clear
+    of the complement of the constraint subspace (eigenvalue 0 of the stored-
+    array operator, at -sigma relative to the physical spectrum)."""
     from . import TERMS_ALL
     full = TERMS_ALL
     terms = full if terms is None else terms

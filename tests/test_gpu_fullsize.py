@@ -113,3 +113,66 @@ def test_large_ragged_grid_jacobian(fvk, bc):
     if bc == 1:
         orc.terms = mask
         assert rel_err(ctx.fv_jacvec(Ud, xd, transpose=True), orc.jacvec_T(U, x)) < TOL
+
+
+def test_100cube_adjoint_config(fvk):
+    """The adjoint workload at 100^3 (tanh grid, synthetic base flow, Pr 0.71,
+    Gr 1e6, conducting walls): the dot-product test <y, A x> = <A^T y, x> on
+    32 seeded pairs of raw random fields, the adjoint Arnoldi for the 4
+    rightmost modes (eigenvalues of A^T = conjugates of those of A, left
+    eigenvectors certified by the oracle's transposed operator), and
+    d lambda / d Gr from the left and right eigenvectors against a central
+    difference of the eigenvalue in Gr with step 1e-4 Gr."""
+    import numpy as np
+    from paper_1905_11601_amd import inputs
+    from paper_1905_11601_amd.adjoint import dlam_dGr, left_eigvecs
+    from paper_1905_11601_amd.eigs import krylov_schur
+    print("case fullsize 100^3 adjoint", flush=True)
+    Gr = 1e6
+    g, orc, ctx = setup((100, 100, 100), TANH, 1.5, 0, Gr=Gr)
+    U = base(g, 0)
+    Ud = dev(U)
+    worst = 0.0
+    for q in range(32):
+        x = dev(torch.as_tensor(inputs.random_fields(g.n, 3000 + q)))
+        y = dev(torch.as_tensor(inputs.random_fields(g.n, 4000 + q)))
+        Ax = ctx.simple_krylov_vec(Ud, x)
+        ATy = ctx.simple_krylov_vec(Ud, y, transpose=True)
+        a, b = ctx.dot(y, Ax), ctx.dot(ATy, x)
+        scale = (ctx.dot(y, y) * ctx.dot(Ax, Ax)) ** 0.5
+        worst = max(worst, abs(a - b) / scale)
+    print("dot test worst", worst, flush=True)
+    assert worst < 1e-14
+    v0 = dev(krylov_input(g, orc, 5000))
+    r = krylov_schur(ctx, Ud, k=4, m=60, v0=v0, tol=1e-10, max_restarts=400)
+    assert r.converged
+    seed = dev(torch.as_tensor(inputs.random_fields(g.n, 5001)))
+    rT, ys = left_eigvecs(ctx, Ud, r.lam, k=4, m=60, seed_vec=seed, tol=1e-10,
+                          max_restarts=400)
+    print("eigs", r.lam, "adjoint eigs", rT.lam, flush=True)
+    assert rT.converged
+    for lam in r.lam:
+        assert np.min(np.abs(rT.lam - np.conj(lam))) < 1e-9 * abs(r.lam[0])
+    # left eigenvector of the leading eigenvalue, certified by the oracle's
+    # transposed operator with the same shift (the left eigenvectors of
+    # A + sigma P are those of A on the constraint subspace, which is all that
+    # d lambda / d Gr = y^H A' x / y^H x sees)
+    yq = ys[0].cpu().numpy().reshape(-1)
+    sig = rT.shift
+    ATy = orc.krylov_vec_T(U, torch.as_tensor(yq.real.reshape(orc.shape4)), shift=sig).numpy() \
+        + 1j * orc.krylov_vec_T(U, torch.as_tensor(yq.imag.reshape(orc.shape4)), shift=sig).numpy()
+    res = np.linalg.norm(ATy.reshape(-1) - (np.conj(r.lam[0]) + sig) * yq) / np.linalg.norm(yq)
+    print("oracle residual of the left eigenvector", res, flush=True)
+    assert res < 1e-9
+    d_adj = dlam_dGr(ctx, Ud, r.X[0], ys[0])
+    step = 1e-4 * Gr
+    lams = []
+    for G2 in (Gr + step, Gr - step):
+        ctx.set_params(G2)
+        rr = krylov_schur(ctx, Ud, k=4, m=60, v0=v0, tol=1e-10, max_restarts=400,
+                          vectors=False)
+        lams.append(rr.lam[int(np.argmin(np.abs(rr.lam - r.lam[0])))])
+    ctx.set_params(Gr)
+    d_fd = (lams[0] - lams[1]) / (2 * step)
+    print("dlam/dGr adjoint", d_adj, "central difference", d_fd, flush=True)
+    assert abs(d_adj - d_fd) < 1e-5 * abs(d_fd)

@@ -74,6 +74,85 @@ def test_simple_krylov_vec(fvk, n, kind, s, bc):
     assert rel_err(p, pref) < TOL
 
 
+SHIFT_CASES = [((6, 5, 7), TANH, 1.5, 0), ((20, 20, 20), UNIFORM, 0.0, 0),
+               ((70, 67, 65), TANH, 1.5, 0), ((24, 20, 28), TANH, 1.5, 1)]
+
+
+@pytest.mark.parametrize("n,kind,s,prec", SHIFT_CASES,
+                         ids=["6x5x7", "20-uniform", "70x67x65", "24x20x28-mixed"])
+@pytest.mark.parametrize("bc", [0, 1], ids=["CC", "AA"])
+def test_shifted_krylov_vec(fvk, n, kind, s, prec, bc):
+    """fvk_set_shift: simple_krylov_vec applies P (J + sigma I) = A + sigma P
+    and its transpose, against the oracle's shifted operator, for an input in
+    the constraint subspace and one that is not (random fields: walls,
+    gradient part), forward and transposed; the shift leaves fv_jacvec and
+    the linear solves unshifted."""
+    print(f"case shifted krylov_vec n={n} bc={bc} prec={prec}", flush=True)
+    g, orc, ctx = setup(n, kind, s, bc, prec=prec)
+    U = base(g, bc)
+    sigma = 3.25
+    ctx.set_shift(sigma)
+    for x in (krylov_input(g, orc, 2000), krylov_input(g, orc, 2001, project=False)):
+        y = ctx.simple_krylov_vec(dev(U), dev(x))
+        assert rel_err(y, orc.krylov_vec(U, x, shift=sigma)) < TOL
+        yT = ctx.simple_krylov_vec(dev(U), dev(x), transpose=True)
+        assert rel_err(yT, orc.krylov_vec_T(U, x, shift=sigma)) < TOL
+    Jx = ctx.fv_jacvec(dev(U), dev(x))
+    assert rel_err(Jx, ops.jacvec(g, orc.prm, U, x)) < TOL
+    ctx.set_shift(0.0)
+    assert rel_err(ctx.simple_krylov_vec(dev(U), dev(x)), orc.krylov_vec(U, x)) < TOL
+
+
+# Thin boxes whose long axis selects each TPF transform variant (even/odd
+# half length ne = ceil(N/2); one wave per 16 rows of ne):
+#   FP64, x axis (divergence-forming forward, operand roles swapped):
+#     180 -> divergence-forming 6 waves, register-resident 6-wave inverse;
+#     210 -> divergence-forming 7 waves, register-resident 8-wave inverse;
+#     300 / 400 -> separate divergence kernel, 12- / 16-wave streaming;
+#     520 -> separate divergence kernel, full-matrix transform (> 512 cells);
+#   FP64, y and z axes: 180 (resident 6 waves), 300 (12), 400 (16), 520 (full,
+#     with the eigenvalue scaling on z);
+#   FP32 (mixed): 40, 80, 130/160, 180 (2, 3, 5, 6-wave streaming and the
+#     divergence-forming variants), 210 (divergence-forming 7 waves, resident
+#     8-wave inverse), 300, 400, 520 on each axis.
+VARIANT_CASES = [
+    ((180, 5, 4), 0), ((210, 4, 5), 0), ((300, 4, 3), 0), ((400, 4, 3), 0), ((520, 4, 3), 0),
+    ((4, 180, 5), 0), ((5, 4, 300), 0), ((3, 400, 4), 0), ((4, 3, 520), 0),
+    ((40, 6, 5), 1), ((80, 5, 6), 1), ((130, 5, 4), 1), ((160, 6, 5), 1), ((180, 4, 5), 1),
+    ((210, 4, 3), 1), ((300, 4, 3), 1), ((520, 3, 4), 1), ((5, 160, 4), 1), ((4, 5, 180), 1),
+    ((3, 4, 400), 1), ((4, 520, 3), 1), ((6, 4, 80), 1),
+]
+
+
+@pytest.mark.parametrize("n,prec", VARIANT_CASES,
+                         ids=[f"{'x'.join(map(str, c[0]))}-{'mixed' if c[1] else 'fp64'}"
+                              for c in VARIANT_CASES])
+def test_transform_variants(fvk, n, prec):
+    """Projection and Krylov vector (forward and transposed) on the boxes
+    that select every transform kernel a legal grid size can reach."""
+    print(f"case transform variant n={n} prec={prec}", flush=True)
+    bc = 1 if n[1] > 100 else 0
+    g, orc, ctx = setup(n, TANH, 1.5, bc, prec=prec)
+    U = base(g, bc)
+    x = krylov_input(g, orc, 2001, project=False)
+    assert rel_err(ctx.project(dev(x)), orc.project(x)) < TOL
+    tolT = TOL if prec == 0 else 1e-9
+    assert rel_err(ctx.project(dev(x), transpose=True), orc.project_T(x)) < tolT
+    xs = krylov_input(g, orc, 2000)
+    y, passes, dmax = ctx.simple_krylov_vec(dev(U), dev(xs), info=True)
+    # one FP64 pass is exact up to rounding, whose divergence floor grows with
+    # the axis length on these stretched grids: past 400 cells it can reach
+    # the 1e-9 test (the oracle itself needs a second pass on 4 x 3 x 520)
+    if prec == 0:
+        assert passes == 1 or (max(n) > 400 and passes == 2)
+    else:
+        assert passes >= 2
+    assert dmax < 1e-9
+    assert rel_err(y, orc.krylov_vec(U, xs)) < TOL
+    yT = ctx.simple_krylov_vec(dev(U), dev(xs), transpose=True)
+    assert rel_err(yT, orc.krylov_vec_T(U, xs)) < tolT
+
+
 def test_asynchronous_calls_record_divergence(fvk):
     g, orc, ctx = setup((12, 12, 12), TANH, 1.5, 0)
     U = dev(base(g, 0))
