@@ -243,6 +243,18 @@ fvk_status fvk_timing_read(fvk_ctx *ctx, double *ms, int *counts);
 /* out[q] = <V_q, w> for q < m over n doubles (host out). */
 fvk_status fvk_multidot(fvk_ctx *ctx, const double *V, size_t ldv, int m, const double *w,
                         size_t n, double *out);
+/* For callers that cannot allocate device memory while they run (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the dot products of fvk_multidot, out_dev[q] = <V_q, w> for q < m, written
+ * to DEVICE memory (out_dev, m doubles) in stream order, without any
+ * allocation, copy to the host or synchronisation.  The block partials live
+ * in a static device array of 2 MiB per GPU (1024 blocks x 256 vectors),
+ * held until the process ends and shared by every call on that GPU: calls
+ * that overlap on one GPU (two streams, two contexts) race on it.  m must be
+ * 1 .. 256 (FVK_EINVAL otherwise); ldv >= n when m > 1.  Same kernels and
+ * summation order as fvk_multidot, so the results are identical. */
+fvk_status fvk_multidot_noalloc(fvk_ctx *ctx, const double *V, size_t ldv, int m,
+                                const double *w, size_t n, double *out_dev);
 /* w <- alpha w + sum_q c[q] V_q (c host, m entries). */
 fvk_status fvk_multiaxpy(fvk_ctx *ctx, double *w, double alpha, const double *V, size_t ldv,
                          int m, const double *c, size_t n);

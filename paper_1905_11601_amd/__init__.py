@@ -240,6 +240,16 @@ class Ctx:
                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
 
+    def multidot_noalloc(self, V, m, w, out, n=None):
+        """out[:m] <- V[:m] . w on the device, no allocation, no sync
+        (fvk_multidot_noalloc); n defaults to the vector length."""
+        n = self.N if n is None else int(n)
+        if not (out.is_cuda and out.dtype == self.torch.float64 and out.numel() >= m):
+            raise ValueError("out: float64 CUDA tensor with at least m entries")
+        self._check(self.lib.fvk_multidot_noalloc(self.h, _ptr(V), V.shape[-1], m, _ptr(w), n,
+                                                  _ptr(out)))
+        return out
+
     def dot(self, x, y):
         return float(self.multidot(x.reshape(1, -1), 1, y)[0])
 

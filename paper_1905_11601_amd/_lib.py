@@ -61,6 +61,8 @@ SIGNATURES = {
     "fvk_timing_read": (c_int, [c_void_p, P(c_double), P(c_int)]),
     "fvk_multidot": (c_int, [c_void_p, c_void_p, c_size_t, c_int, c_void_p, c_size_t,
                              P(c_double)]),
+    "fvk_multidot_noalloc": (c_int, [c_void_p, c_void_p, c_size_t, c_int, c_void_p, c_size_t,
+                                     c_void_p]),
     "fvk_multiaxpy": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_size_t, c_int,
                               P(c_double), c_size_t]),
     "fvk_axpby": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_double, c_size_t]),

@@ -425,6 +425,12 @@ fvk_status fvk_create(fvk_ctx **out, int nx, int ny, int nz, int grid_kind, doub
         st = fail(ctx, FVK_EHIP, "geometry upload failed");
         goto bad;
     }
+    // device address of the non-allocating entry point's static scratch on
+    // this device (once per device)
+    if (!noalloc_prepare(&ctx->err)) {
+        st = FVK_EHIP;
+        goto bad;
+    }
     for (int a = 0; a < 3; ++a) {
         g.ax[a].ih = w.geo + off[a][0] + 1;
         g.ax[a].id = w.geo + off[a][1] + 1;

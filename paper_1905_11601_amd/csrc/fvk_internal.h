@@ -172,6 +172,11 @@ void launch_ext_T(const Geo &g, int span_aa, const double *src, double *dst, hip
 void launch_ext_T_T(const Geo &g, int span_aa, const double *src, double *dst, hipStream_t st);
 void launch_zero_vel_walls(const Geo &g, const double *src, double *dst, hipStream_t st);
 
+// ---- static scratch of the non-allocating entry point (noalloc.hip): looks
+// up its device address on the current device once; false with a message on
+// failure
+bool noalloc_prepare(std::string *err);
+
 // ---- TPF (kernels_tpf.hip)
 // phi = L^+ b by the TPF transforms.  With vel != nullptr (only where
 // tpf_fuses_div), b is not read: the right-hand side is D vel (win: D W^-1 vel)
