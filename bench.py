@@ -18,10 +18,13 @@ Prints one JSON line: value = Krylov vectors per second, a roofline entry for
 the dominant kernel (timed live with HIP events on the library's stream, one
 context at a time so that the kernel durations are those of the kernels
 alone) and a CPU baseline of the oracle on a bounded sample of the same
-workload.
+workload.  Besides the headline 100^3 value the line carries the other half
+of the metric: `n256` (FP64, mixed-precision and adjoint rates at 256^3 with
+their per-stage roofline) and `lambda_error` (the rightmost eigenvalues at
+100^3 in FP64 and in mixed precision, and their difference).
 
 Usage: python bench.py [--steps K] [--warmup W] [--n N] [--nvec M]
-       [--streams S] [--no-cpu-baseline] [--no-extra]
+       [--streams S] [--no-cpu-baseline] [--no-extra] [--no-eig] [--no-256]
        python bench.py --copy-calibration          (a 2 GiB device copy, for
                                                     rocprofv3 --pmc scaling)
        python bench.py --ingest-pmc FETCH WRITE CFETCH CWRITE
@@ -174,9 +177,26 @@ def traffic_entry(n):
     return rec["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(n, nvec_sample):
+def host_info():
+    """Host CPU facts for the baseline: logical CPUs visible to this process
+    and the CPU model (lscpu)."""
+    import subprocess
+    info = {"nproc": len(os.sched_getaffinity(0)), "cpu_count": os.cpu_count()}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in txt.splitlines():
+            key, _, val = line.partition(":")
+            if key.strip() in ("Model name", "Socket(s)", "Core(s) per socket", "Thread(s) per core"):
+                info[key.strip()] = val.strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return info
+
+
+def cpu_baseline(n, min_seconds, one_thread_seconds):
     """The oracle on the host cores: simple_krylov_vec of the same workload on
-    a bounded sample (nvec_sample vectors, CC walls)."""
+    a bounded sample (as many calls as fit in min_seconds, CC walls), then the
+    same with one thread."""
     import torch
     from oracle import ops
     from oracle.grid import Grid, TANH
@@ -189,19 +209,37 @@ def cpu_baseline(n, nvec_sample):
     h = tuple(a.h for a in g.ax)
     U = torch.as_tensor(inputs.synthetic_base(f, c, h, 0))
     xs = []
-    ndistinct = min(nvec_sample, 16)   # inputs reused cyclically (host memory)
+    ndistinct = 16   # inputs reused cyclically (host memory)
     for q in range(ndistinct):
         x = orc.project(torch.as_tensor(inputs.random_fields(g.n, 2000 + q)))
         xs.append(x / torch.linalg.norm(x))
-    orc.krylov_vec(U, xs[0])                      # warm-up
-    t0 = time.perf_counter()
-    for q in range(nvec_sample):
-        orc.krylov_vec(U, xs[q % ndistinct])
-    dt = time.perf_counter() - t0
-    return {"value": nvec_sample / dt, "unit": "Krylov vectors/s", "cores": torch.get_num_threads(),
-            "kind": "oracle",
-            "sample": f"{nvec_sample} simple_krylov_vec calls at {n}^3 ({ndistinct} distinct seeded "
-                      f"unit inputs, cyclic), CC walls, PyTorch CPU FP64 oracle, {dt:.1f} s"}
+    def rate(seconds):
+        orc.krylov_vec(U, xs[0])                  # warm-up
+        t0 = time.perf_counter()
+        calls = 0
+        while True:
+            orc.krylov_vec(U, xs[calls % ndistinct])
+            calls += 1
+            dt = time.perf_counter() - t0
+            if dt >= seconds and calls >= 4:
+                return calls, dt
+
+    threads = torch.get_num_threads()
+    calls, dt = rate(min_seconds)
+    out = {"value": calls / dt, "unit": "Krylov vectors/s", "cores": threads, "kind": "oracle",
+           "sample": f"{calls} simple_krylov_vec calls at {n}^3 ({ndistinct} distinct seeded "
+                     f"unit inputs, cyclic), CC walls, PyTorch CPU FP64 oracle on {threads} "
+                     f"threads, {dt:.1f} s",
+           "host": host_info()}
+    if one_thread_seconds > 0:
+        torch.set_num_threads(1)
+        try:
+            c1, d1 = rate(one_thread_seconds)
+        finally:
+            torch.set_num_threads(threads)
+        out["one_thread"] = {"value": c1 / d1, "unit": "Krylov vectors/s", "cores": 1,
+                             "sample": f"{c1} calls, {d1:.1f} s"}
+    return out
 
 
 def main():
@@ -215,7 +253,14 @@ def main():
                     help="1: both wall variants on one stream; 2: one stream each; "
                          "0 (default): 2 up to 160^3 cells, else 1")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=480)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="oracle baseline: time budget of the all-threads sample")
+    ap.add_argument("--cpu-one-thread-seconds", type=float, default=8.0)
+    ap.add_argument("--no-256", action="store_true",
+                    help="skip the 256^3 leg (FP64, mixed and adjoint rates at 256^3)")
+    ap.add_argument("--nvec-256", type=int, default=8)
+    ap.add_argument("--no-eig", action="store_true",
+                    help="skip the eigenvalue-error leg (FP64 vs mixed Krylov-Schur)")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the mixed-precision, adjoint and Arnoldi-step rates")
     ap.add_argument("--copy-calibration", action="store_true")
@@ -353,10 +398,138 @@ def main():
     if not args.no_extra:
         log("extra rates")
         out["extra"] = extra_rates(fvk, torch, runs, args)
+    if not args.no_eig:
+        log("eigenvalue error: FP64 vs mixed Krylov-Schur")
+        out["lambda_error"] = eigen_leg(fvk, torch, runs[0][0], runs[0][1])
+    del runs, Ys
+    torch.cuda.empty_cache()
+    if not args.no_256 and n != 256:
+        log("256^3 leg")
+        out["n256"] = leg_256(fvk, torch, args.nvec_256, max(1, min(args.steps, 3)))
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(n, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds, args.cpu_one_thread_seconds)
     print(json.dumps(out))
+
+
+def stage_roofline(per_us, n):
+    """Roofline fractions of the stages of one FP64 Krylov vector at n^3 from
+    their average launch durations (us): the Jacobian stencil and the
+    correction against HBM (algorithmic bytes), the axis transforms against
+    whichever of HBM and FP64 MFMA is tighter for their size."""
+    npts, ncell = (n + 2) ** 3, n ** 3
+    out = {}
+    for k, nbytes in (("jacvec", stencil_bytes_per_point() * npts),
+                      ("correct", (3 + 3 + 1) * 8 * ncell + 3 * 8 * npts)):
+        if per_us.get(k):
+            gbs = nbytes / (per_us[k] * 1e-6) / 1e9
+            out[k] = {"us": per_us[k], "GB/s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}
+    if per_us.get("transform"):
+        flops, nbytes = transform_work(n)
+        t = per_us["transform"] * 1e-6
+        out["transform"] = {"us": per_us["transform"], "GB/s": nbytes / t / 1e9,
+                            "frac_hbm": nbytes / t / 1e9 / HBM_PEAK_GBS,
+                            "TFLOP/s": flops / t / 1e12,
+                            "frac_fp64_mfma": flops / t / 1e12 / FP64_PEAK_TFS}
+    return out
+
+
+def leg_256(fvk, torch, nvec, reps):
+    """The 256^3 half of the metric: FP64, mixed-precision and transposed
+    (adjoint) Krylov-vector rates on nvec seeded unit inputs for each wall
+    variant (one context and one stream each, vectors back to back, as an
+    Arnoldi or GMRES iteration issues them), and the per-stage roofline of the
+    FP64 vector from HIP events."""
+    from paper_1905_11601_amd import inputs
+    n = 256
+    raws = [torch.as_tensor(inputs.random_fields((n, n, n), 2000 + q)) for q in range(nvec)]
+    kinds = (("fp64", fvk.FP64, False), ("mixed", fvk.MIXED, False),
+             ("fp64_adjoint", fvk.FP64, True), ("mixed_adjoint", fvk.MIXED, True))
+    acc = {k: [0, 0.0] for k, _, _ in kinds}
+    stages = {}
+    max_div = 0.0
+    n_bad = 0
+    records = {}
+    for bc in (fvk.CC, fvk.AA):
+        ctx = fvk.Ctx(n, grid=fvk.TANH, s=1.5, span_bc=bc, Gr=1e6, Pr=0.71)
+        f, c, h = ctx.coords()
+        base = torch.as_tensor(inputs.synthetic_base(f, c, h, bc)).cuda()
+        X = torch.empty((nvec,) + ctx.shape4, dtype=torch.float64, device="cuda")
+        for q in range(nvec):
+            ctx.project(raws[q].cuda(), out=X[q])
+            ctx.normalize(X[q])
+        Y = torch.empty_like(X)
+        ctx.simple_stats()
+
+        def run(tr):
+            for q in range(nvec):
+                ctx.simple_krylov_vec(base, X[q], out=Y[q], transpose=tr)
+
+        wall = "CC" if bc == fvk.CC else "AA"
+        for key, prec, tr in kinds:
+            ctx.set_precision(prec)
+            run(tr)
+            ms = timed(torch, lambda: run(tr), reps)
+            acc[key][0] += nvec
+            acc[key][1] += ms / 1e3
+            if not tr:
+                # the divergence records of this precision's asynchronous calls
+                d, bad = ctx.simple_stats()
+                records[f"{wall}_{key}"] = {"max_div": d, "calls_above_tol": bad,
+                                            "passes": (ctx.mixed_passes()[0]
+                                                       if prec == fvk.MIXED else 1)}
+                max_div = max(max_div, d)
+                n_bad += bad
+        ctx.set_precision(fvk.FP64)
+        ctx.set_timing(("jacvec", "div", "transform", "correct"))
+        for _ in range(reps):
+            run(False)
+        for k, (ms, cnt) in ctx.timing_read().items():
+            a = stages.setdefault(k, [0.0, 0])
+            a[0] += ms
+            a[1] += cnt
+        ctx.set_timing(())
+        ctx.simple_stats()
+        del X, Y, base
+        ctx.close()
+        torch.cuda.empty_cache()
+    per_us = {k: 1e3 * v[0] / v[1] for k, v in stages.items() if v[1]}
+    rates = {f"{k}_vec_per_s": v[0] / v[1] for k, v in acc.items()}
+    return {"grid": n, "vectors_per_wall_variant": nvec, "walls": ["CC", "AA"],
+            "streams": 1, **rates, "max_div_after_simple": max_div,
+            "calls_above_simple_tol": n_bad, "divergence_records": records,
+            "stages_us_per_launch": per_us, "roofline": stage_roofline(per_us, n)}
+
+
+def eigen_leg(fvk, torch, ctx, base, k=4, m=100, tol=1e-9):
+    """The eigenvalue accuracy the rates are quoted at: the k rightmost
+    eigenvalues of the 100^3 CC problem by Krylov-Schur (Krylov dimension m)
+    in FP64 and in mixed precision from the same start vector, their Ritz
+    residuals, and the largest mixed-vs-FP64 difference."""
+    import numpy as np
+    from paper_1905_11601_amd import inputs
+    from paper_1905_11601_amd.eigs import krylov_schur
+    with torch.cuda.stream(ctx.stream):
+        v0 = ctx.project(torch.as_tensor(inputs.random_fields(ctx.n, 5000)).cuda())
+        out = {"workload": f"{k} rightmost eigenvalues, {ctx.n[0]}^3 CC, Krylov dimension {m}, "
+                           f"Ritz residual tolerance {tol:g}, start vector seed 5000"}
+        lams = {}
+        for name, prec in (("fp64", fvk.FP64), ("mixed", fvk.MIXED)):
+            ctx.set_precision(prec)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = krylov_schur(ctx, base, k=k, m=m, v0=v0, tol=tol, max_restarts=400,
+                             vectors=False)
+            torch.cuda.synchronize()
+            lams[name] = r.lam
+            out[name] = {"eigenvalues": [[float(v.real), float(v.imag)] for v in r.lam],
+                         "ritz_residual_max": float(np.max(r.res)), "converged": r.converged,
+                         "krylov_vectors": r.nvec, "seconds": time.perf_counter() - t0}
+        ctx.set_precision(fvk.FP64)
+    d = [float(np.min(np.abs(lams["fp64"] - l))) for l in lams["mixed"]]
+    out["mixed_vs_fp64_max_abs"] = max(d)
+    out["mixed_vs_fp64_max_rel"] = max(d) / float(np.abs(lams["fp64"]).max())
+    return out
 
 
 def timed(torch, fn, reps):

@@ -170,12 +170,22 @@ fvk_status fvk_project(fvk_ctx *ctx, const double *x, double *y, int transpose);
  * correction.  If `passes` or `max_div` is non-NULL the call synchronises and
  * reports the SIMPLE pass count and the final max |D v|; if both are NULL the
  * call is asynchronous and the divergence check is recorded on the device
- * (fvk_simple_stats).  Returns FVK_ENOCONV when the pass cap is hit.  The
- * transposed call always runs the fixed pass count (its internal divergence,
- * of W^-1 x, is reported but not tested and not recorded).
+ * (fvk_simple_stats).  Returns FVK_ENOCONV when the pass cap is hit.  In
+ * FP64 one pass is exact up to rounding; in mixed precision asynchronous
+ * calls run a fixed number of FP32 solves with FP64 refinement passes: the
+ * number the first asynchronous forward mixed call of the context needed
+ * (that call runs the adaptive loop synchronously; one more if its final
+ * divergence came within a factor 10 of the tolerance; at least 2; reset by
+ * fvk_set_simple; see fvk_mixed_passes), and every call's divergence test is
+ * still recorded.  The transposed call always runs the fixed pass count (its
+ * internal divergence, of W^-1 x, is reported but not tested and not
+ * recorded).
  * x and y must not overlap. */
 fvk_status simple_krylov_vec(fvk_ctx *ctx, const double *base, const double *x, double *y,
                              double *p_out, int transpose, int *passes, double *max_div);
+/* The fixed pass count of asynchronous mixed-precision calls and whether it
+ * has been calibrated by an adaptive call (see simple_krylov_vec). */
+fvk_status fvk_mixed_passes(const fvk_ctx *ctx, int *passes, int *calibrated);
 /* Largest max |D v| seen by asynchronous forward calls since the last query,
  * and the number of such calls that needed more passes than the fixed count.
  * Resets.  The device keeps each asynchronous call's block maxima and reduces

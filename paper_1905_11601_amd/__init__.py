@@ -182,6 +182,13 @@ class Ctx:
         self._check(self.lib.fvk_simple_stats(self.h, ctypes.byref(d), ctypes.byref(k)))
         return d.value, k.value
 
+    def mixed_passes(self):
+        """(fixed pass count of asynchronous mixed calls, calibrated?)"""
+        k = ctypes.c_int()
+        c = ctypes.c_int()
+        self._check(self.lib.fvk_mixed_passes(self.h, ctypes.byref(k), ctypes.byref(c)))
+        return k.value, bool(c.value)
+
     STAGES = ("jacvec", "div", "transform", "correct", "ortho")
 
     def set_timing(self, stages=()):

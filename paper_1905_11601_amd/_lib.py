@@ -52,6 +52,7 @@ SIGNATURES = {
     "fvk_project": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
     "simple_krylov_vec": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
                                   P(c_int), P(c_double)]),
+    "fvk_mixed_passes": (c_int, [c_void_p, P(c_int), P(c_int)]),
     "fvk_simple_stats": (c_int, [c_void_p, P(c_double), P(c_int)]),
     "arnoldi_step": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_int, P(c_double), c_int]),
     "arnoldi_step_lagged": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_int, P(c_double),

@@ -138,8 +138,14 @@ fvk_status simple_forward(fvk_ctx *ctx, const double *vin, double *vout, double 
     // that of the internal field W^-1 y, whose size (and rounding floor) has
     // no relation to the absolute tolerance of the physical velocity;
     // passes/div are still reported
-    const bool want_div = sync;
+    bool want_div = sync;
     if (transposed) sync = false;
+    // the number of FP32 solves + FP64 refinement passes that reach the
+    // tolerance depends on the grid and the operator's scale (2 at 100^3, 3
+    // at 256^3): the first asynchronous forward call in mixed precision runs
+    // the adaptive loop and fixes the count of the later asynchronous ones
+    const bool calibrate = fp32 && !sync && !transposed && !ctx->mixed_calibrated;
+    if (calibrate) sync = want_div = true;
     if (p_out) launch_fill(p_out, 0.0, ctx->ncell, st);
     // first right-hand side D vin: formed inside the first transform where the
     // x axis allows it, else by the divergence kernel
@@ -206,6 +212,13 @@ fvk_status simple_forward(fvk_ctx *ctx, const double *vin, double *vout, double 
     if (div_out) *div_out = dmax;
     if (sync && !(dmax < ctx->simple_tol))
         return fail(ctx, FVK_ENOCONV, "SIMPLE loop hit its pass cap");
+    if (calibrate) {
+        // vectors differ by a factor ~2 in the divergence a given pass count
+        // leaves (each pass contracts it ~1e-6-fold): a result within 10x of
+        // the tolerance means another vector may miss it, so one pass more
+        ctx->mixed_passes = std::max(2, dmax > 0.1 * ctx->simple_tol ? k + 1 : k);
+        ctx->mixed_calibrated = true;
+    }
     return FVK_OK;
 }
 
@@ -518,6 +531,13 @@ fvk_status fvk_set_precision(fvk_ctx *ctx, int prec) {
     return FVK_OK;
 }
 
+fvk_status fvk_mixed_passes(const fvk_ctx *ctx, int *passes, int *calibrated) {
+    if (!ctx) return FVK_EINVAL;
+    if (passes) *passes = ctx->mixed_passes;
+    if (calibrated) *calibrated = ctx->mixed_calibrated ? 1 : 0;
+    return FVK_OK;
+}
+
 fvk_status fvk_set_simple(fvk_ctx *ctx, double tol, int max_passes) {
     if (!ctx) return FVK_EINVAL;
     if (!(tol > 0) || max_passes < 1 || max_passes > 100)
@@ -525,6 +545,8 @@ fvk_status fvk_set_simple(fvk_ctx *ctx, double tol, int max_passes) {
     flush_ring(ctx);   // the pending records are tested against the old tolerance
     ctx->simple_tol = tol;
     ctx->simple_cap = max_passes;
+    ctx->mixed_calibrated = false;   // recalibrate the asynchronous mixed pass count
+    ctx->mixed_passes = 2;
     return FVK_OK;
 }
 

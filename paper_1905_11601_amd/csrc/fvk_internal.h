@@ -121,6 +121,7 @@ struct fvk_ctx {
     double simple_tol = 1e-9;
     int simple_cap = 10;
     int mixed_passes = 2;           // fixed pass count of asynchronous mixed calls
+    bool mixed_calibrated = false;  // mixed_passes set by an adaptive forward call
     double shift = 0.0;             // fvk_set_shift: Krylov operator A + shift P
     fvk::AxisHost ax[3];
     fvk::Eig1D eig[3];

@@ -176,3 +176,23 @@ def test_100cube_adjoint_config(fvk):
     d_fd = (lams[0] - lams[1]) / (2 * step)
     print("dlam/dGr adjoint", d_adj, "central difference", d_fd, flush=True)
     assert abs(d_adj - d_fd) < 1e-5 * abs(d_fd)
+
+
+def test_100cube_eigenvalues_certified_by_oracle(fvk, capsys):
+    """The 4 rightmost eigenvalues at 100^3 (tanh grid, synthetic base flow,
+    Gr 1e6, conducting walls) by Krylov-Schur with Krylov dimension 100, in
+    FP64 and in mixed precision; every GPU eigenpair certified by the
+    oracle's operator applied on the host, and the mixed-precision
+    eigenvalues within 1e-6 (relative) of the FP64 ones."""
+    import json
+    from tests import certify_eigs
+    print("case fullsize 100^3 certified eigenvalues", flush=True)
+    rc = certify_eigs.main(["--n", "100", "--k", "4", "--m", "100", "--tol", "1e-9",
+                            "--prec", "both", "--max-restarts", "400"])
+    out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    print(json.dumps(out), flush=True)
+    assert rc == 0
+    for prec in ("fp64", "mixed"):
+        assert out[prec]["converged"]
+        assert max(out[prec]["oracle_ritz_residuals"]) < 1e-8
+    assert out["mixed_vs_fp64_max_rel"] < 1e-6

@@ -204,6 +204,26 @@ def test_mixed_precision_krylov_vec(fvk, bc):
     assert rel_err(yT, orc.krylov_vec_T(U, x)) < 1e-9
 
 
+def test_mixed_precision_async_pass_count_calibration(fvk):
+    """Asynchronous mixed-precision calls run a fixed number of refinement
+    passes, fixed by the first such call (run adaptively): afterwards every
+    asynchronous call meets the divergence test and matches the oracle."""
+    g, orc, ctx = setup((40, 36, 44), TANH, 1.5, 0, prec=1)
+    U = dev(base(g, 0))
+    xs = [krylov_input(g, orc, 2010 + q) for q in range(4)]
+    assert ctx.mixed_passes() == (2, False)
+    ctx.simple_stats()
+    ys = [ctx.simple_krylov_vec(U, dev(x)) for x in xs]
+    k, cal = ctx.mixed_passes()
+    assert cal and k >= 2
+    dmax, nbad = ctx.simple_stats()
+    assert nbad == 0 and dmax < 1e-9
+    for x, y in zip(xs, ys):
+        assert rel_err(y, orc.krylov_vec(base(g, 0), x)) < TOL
+    ctx.set_simple(1e-9, 10)           # resets the calibration
+    assert ctx.mixed_passes() == (2, False)
+
+
 def test_vector_kernels(fvk):
     g, orc, ctx = setup((9, 8, 7), TANH, 1.5, 0)
     rng = np.random.default_rng(0)
