@@ -186,6 +186,22 @@ fvk_status simple_krylov_vec(fvk_ctx *ctx, const double *base, const double *x, 
 /* The fixed pass count of asynchronous mixed-precision calls and whether it
  * has been calibrated by an adaptive call (see simple_krylov_vec). */
 fvk_status fvk_mixed_passes(const fvk_ctx *ctx, int *passes, int *calibrated);
+/* Visualisation of a 3D velocity field by divergence-free projections onto
+ * the planes normal to one axis and their vector potentials (Sec. 3.2,
+ * Psi_x, Psi_y, Psi_z).  For axis a (0 = x, 1 = y, 2 = z) with the in-plane
+ * axes (b, c) in cyclic order: vproj (3 stored velocity fields, the layout
+ * of the first three fields of a vector) = the W-orthogonal projection of
+ * vel onto the fields with a zero a-component, zero wall entries and zero
+ * in-plane divergence D_bc in every a-plane (one plane-wise TPF solve, the
+ * 2D analogue of the SIMPLE step, FP64 whatever the context precision);
+ * psi (nullable, one stored field) = the vector potential on the a-edges:
+ * vproj = curl(psi e_a), i.e. vproj_b = d psi / d c, vproj_c = -d psi / d b,
+ * psi = 0 on the walls; entry (i, j, k) holds the edge at cell index
+ * (1..n_a) along a and face indices (0..n) along b and c, other entries 0.
+ * vel may be a 4-field vector (its first three fields are read); vproj may
+ * be vel.  Uses the context's Poisson workspace (stream-ordered). */
+fvk_status fvk_psi_projection(fvk_ctx *ctx, const double *vel, int axis, double *vproj,
+                              double *psi);
 /* Largest max |D v| seen by asynchronous forward calls since the last query,
  * and the number of such calls that needed more passes than the fixed count.
  * Resets.  The device keeps each asynchronous call's block maxima and reduces
@@ -222,6 +238,13 @@ fvk_status arnoldi_step(fvk_ctx *ctx, const double *base, double *V, size_t ldv,
  * V is left as it was. */
 fvk_status arnoldi_step_lagged(fvk_ctx *ctx, const double *base, double *V, size_t ldv, int j,
                                double *H, int ldh, int transpose);
+/* The same step for an operator applied by the caller (a polynomial in A,
+ * e.g. the Chebyshev filter of an accelerated Arnoldi iteration, Sec. 3.1's
+ * Chebyshev-preconditioned eigenvalue solver): slot j+1 must already hold the
+ * operator applied to slot j (the raw vector, as stored); everything else is
+ * as in arnoldi_step_lagged. */
+fvk_status arnoldi_step_lagged_applied(fvk_ctx *ctx, double *V, size_t ldv, int j, double *H,
+                                       int ldh);
 /* Completes a lagged Arnoldi sequence after step j-1: re-orthogonalises and
  * normalises slot j into v_j and corrects row j and the columns of H above it
  * (H as in arnoldi_step_lagged, columns 0..j-1).  Returns FVK_EBREAKDOWN as
@@ -268,6 +291,11 @@ fvk_status fvk_multidot_noalloc(fvk_ctx *ctx, const double *V, size_t ldv, int m
 /* w <- alpha w + sum_q c[q] V_q (c host, m entries). */
 fvk_status fvk_multiaxpy(fvk_ctx *ctx, double *w, double alpha, const double *V, size_t ldv,
                          int m, const double *c, size_t n);
+/* z <- a x + b y + c z over n doubles (z must alias neither x nor y); the
+ * three-term recurrence of polynomial filters, enqueued without any host
+ * transfer. */
+fvk_status fvk_lincomb3(fvk_ctx *ctx, double *z, double a, const double *x, double b,
+                        const double *y, double c, size_t n);
 /* y <- a x + b y over n doubles (x == y allowed: scaling). */
 fvk_status fvk_axpby(fvk_ctx *ctx, double *y, double a, const double *x, double b, size_t n);
 /* V[:, 0..k) <- V[:, 0..m) Q with Q host, column-major m x k (k <= m), in place

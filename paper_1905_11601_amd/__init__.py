@@ -176,6 +176,19 @@ class Ctx:
                                                None, None))
         return out
 
+    def psi_projection(self, vel, axis):
+        """(vproj, psi) for the planes normal to `axis` (fvk_psi_projection):
+        vproj a (3, nz+2, ny+2, nx+2) tensor, psi one stored field.  vel: a
+        4-field vector (or 3 velocity fields) on the device."""
+        torch = self.torch
+        if not (isinstance(vel, torch.Tensor) and vel.dtype == torch.float64 and vel.is_cuda
+                and vel.is_contiguous() and vel.numel() in (self.N, 3 * self.F)):
+            raise ValueError("vel: contiguous float64 CUDA tensor of 3 or 4 fields")
+        vp = torch.empty((3,) + self.shape4[1:], dtype=torch.float64, device=self.device)
+        psi = torch.empty(self.shape4[1:], dtype=torch.float64, device=self.device)
+        self._check(self.lib.fvk_psi_projection(self.h, _ptr(vel), int(axis), _ptr(vp), _ptr(psi)))
+        return vp, psi
+
     def simple_stats(self):
         d = ctypes.c_double()
         k = ctypes.c_int()
@@ -231,6 +244,25 @@ class Ctx:
         self._check(self.lib.arnoldi_step_lagged(self.h, self._vec(base, "base"), _ptr(V),
                                                  V.shape[1], j, self._hess(H), H.shape[1],
                                                  int(bool(transpose))))
+
+    def arnoldi_step_lagged_applied(self, V, j, H):
+        """Lagged-CGS2 step j for an operator applied by the caller: V[j+1]
+        already holds it applied to V[j]."""
+        if V.dim() != 2 or V.shape[1] != self.N or not V.is_contiguous() or j + 1 >= V.shape[0]:
+            raise ValueError("V must be a contiguous (m+1, N) tensor with room for vector j+1")
+        if H.shape[0] < j + 2 or H.shape[1] < j + 1:
+            raise ValueError("H too small for step j")
+        self._check(self.lib.arnoldi_step_lagged_applied(self.h, _ptr(V), V.shape[1], j,
+                                                         self._hess(H), H.shape[1]))
+
+    def lincomb3(self, z, a, x, b, y, c):
+        """z <- a x + b y + c z (library kernel, no host transfer)."""
+        if not (z.numel() == x.numel() == y.numel()) or not all(
+                t.is_contiguous() for t in (x, y, z)):
+            raise ValueError("lincomb3: contiguous tensors of equal size")
+        self._check(self.lib.fvk_lincomb3(self.h, _ptr(z), float(a), _ptr(x), float(b), _ptr(y),
+                                          float(c), z.numel()))
+        return z
 
     def arnoldi_finish(self, V, j, H):
         """Completes a lagged sequence: slot j becomes the unit vector v_j."""

@@ -53,10 +53,15 @@ SIGNATURES = {
     "simple_krylov_vec": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int,
                                   P(c_int), P(c_double)]),
     "fvk_mixed_passes": (c_int, [c_void_p, P(c_int), P(c_int)]),
+    "fvk_psi_projection": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_void_p]),
     "fvk_simple_stats": (c_int, [c_void_p, P(c_double), P(c_int)]),
     "arnoldi_step": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_int, P(c_double), c_int]),
     "arnoldi_step_lagged": (c_int, [c_void_p, c_void_p, c_void_p, c_size_t, c_int, P(c_double),
                                     c_int, c_int]),
+    "arnoldi_step_lagged_applied": (c_int, [c_void_p, c_void_p, c_size_t, c_int, P(c_double),
+                                            c_int]),
+    "fvk_lincomb3": (c_int, [c_void_p, c_void_p, c_double, c_void_p, c_double, c_void_p,
+                             c_double, c_size_t]),
     "arnoldi_finish": (c_int, [c_void_p, c_void_p, c_size_t, c_int, P(c_double), c_int]),
     "fvk_set_timing": (c_int, [c_void_p, c_int]),
     "fvk_timing_read": (c_int, [c_void_p, P(c_double), P(c_int)]),

@@ -73,6 +73,7 @@ void free_ws(fvk_ctx *ctx) {
     fr(w.dev_counters);
     fr(w.div_slots);
     fr(w.coef_dev);
+    fr(w.zeros);
     if (w.host_pinned) (void)hipHostFree(w.host_pinned);
     w = Workspace();
 }
@@ -377,6 +378,12 @@ fvk_status fvk_create(fvk_ctx **out, int nx, int ny, int nz, int grid_kind, doub
     if ((st = dalloc(ctx, &w.div_slots, 4)) != FVK_OK) goto bad;
     w.coef_len = 65536;
     if ((st = dalloc(ctx, &w.coef_dev, w.coef_len)) != FVK_OK) goto bad;
+    if ((st = dalloc(ctx, &w.zeros, size_t(std::max(nx, std::max(ny, nz))))) != FVK_OK) goto bad;
+    if (hipMemset(w.zeros, 0, sizeof(double) * size_t(std::max(nx, std::max(ny, nz)))) !=
+        hipSuccess) {
+        st = fail(ctx, FVK_EHIP, "zeroing failed");
+        goto bad;
+    }
     w.host_pinned_len = 65536;
     if (hipHostMalloc(reinterpret_cast<void **>(&w.host_pinned),
                       w.host_pinned_len * sizeof(double), 0) != hipSuccess) {
@@ -673,6 +680,20 @@ fvk_status simple_krylov_vec(fvk_ctx *ctx, const double *base, const double *x, 
     return FVK_OK;
 }
 
+fvk_status fvk_psi_projection(fvk_ctx *ctx, const double *vel, int axis, double *vproj,
+                              double *psi) {
+    if (!ctx || !vel || !vproj || axis < 0 || axis > 2) return FVK_EINVAL;
+    const Geo &g = ctx->geo;
+    Workspace &w = ctx->ws;
+    hipStream_t st = ctx->stream;
+    launch_div_plane(g, vel, w.div, axis, st);
+    tpf_solve_plane(ctx, w.div, w.phi, axis, st);
+    launch_correct_plane(g, vel, w.phi, vproj, axis, st);
+    if (psi) launch_psi_lines(g, vproj, psi, axis, st);
+    CHECK_LAUNCH(ctx);
+    return FVK_OK;
+}
+
 fvk_status fvk_simple_stats(fvk_ctx *ctx, double *max_div, int *n_unconverged) {
     if (!ctx) return FVK_EINVAL;
     flush_ring(ctx);
@@ -814,18 +835,58 @@ fvk_status lag_finalise(fvk_ctx *ctx, int j, double *H, int ldh, const double *d
 
 extern "C" {
 
-fvk_status arnoldi_step_lagged(fvk_ctx *ctx, const double *base, double *V, size_t ldv, int j,
-                               double *H, int ldh, int transpose) {
-    if (!ctx || !base || !V || !H || j < 0 || ldh < j + 1) return FVK_EINVAL;
+static fvk_status lagged_check(fvk_ctx *ctx, size_t ldv, int j) {
     const size_t n = nvec(ctx);
     if (ldv < n) return fail(ctx, FVK_EINVAL, "ldv smaller than the vector length");
     const int m2 = j + 2;   // rows v_0..v_{j-1}, slot j, slot j+1
     const int nb = multidot2_blocks(n);
     if (size_t(nb) * 2 * m2 > ctx->ws.red_len || 2 * m2 + 8 > 4096 || 2 * j > int(ctx->ws.coef_len))
         return fail(ctx, FVK_EINVAL, "Krylov dimension too large");
-    double *x = V + size_t(j) * ldv, *w = V + size_t(j + 1) * ldv;
-    fvk_status s = simple_krylov_vec(ctx, base, x, w, nullptr, transpose, nullptr, nullptr);
+    return FVK_OK;
+}
+
+static fvk_status lagged_orthogonalise(fvk_ctx *ctx, double *V, size_t ldv, int j, double *H,
+                                       int ldh);
+
+fvk_status arnoldi_step_lagged(fvk_ctx *ctx, const double *base, double *V, size_t ldv, int j,
+                               double *H, int ldh, int transpose) {
+    if (!ctx || !base || !V || !H || j < 0 || ldh < j + 1) return FVK_EINVAL;
+    fvk_status s = lagged_check(ctx, ldv, j);
     if (s != FVK_OK) return s;
+    double *x = V + size_t(j) * ldv, *w = V + size_t(j + 1) * ldv;
+    s = simple_krylov_vec(ctx, base, x, w, nullptr, transpose, nullptr, nullptr);
+    if (s != FVK_OK) return s;
+    return lagged_orthogonalise(ctx, V, ldv, j, H, ldh);
+}
+
+fvk_status arnoldi_step_lagged_applied(fvk_ctx *ctx, double *V, size_t ldv, int j, double *H,
+                                       int ldh) {
+    if (!ctx || !V || !H || j < 0 || ldh < j + 1) return FVK_EINVAL;
+    fvk_status s = lagged_check(ctx, ldv, j);
+    if (s != FVK_OK) return s;
+    return lagged_orthogonalise(ctx, V, ldv, j, H, ldh);
+}
+
+fvk_status fvk_lincomb3(fvk_ctx *ctx, double *z, double a, const double *x, double b,
+                        const double *y, double c, size_t n) {
+    if (!ctx || !z || !x || !y || n == 0) return FVK_EINVAL;
+    if (z == x || z == y) return fail(ctx, FVK_EINVAL, "z must not alias x or y");
+    launch_lincomb3(z, a, x, b, y, c, n, ctx->stream);
+    CHECK_LAUNCH(ctx);
+    return FVK_OK;
+}
+
+}  // extern "C"
+
+// the lagged-CGS2 update of step j once slot j+1 holds the operator applied to
+// slot j (see arnoldi_step_lagged)
+static fvk_status lagged_orthogonalise(fvk_ctx *ctx, double *V, size_t ldv, int j, double *H,
+                                       int ldh) {
+    const size_t n = nvec(ctx);
+    const int m2 = j + 2;
+    const int nb = multidot2_blocks(n);
+    double *x = V + size_t(j) * ldv, *w = V + size_t(j + 1) * ldv;
+    fvk_status s = FVK_OK;
     hipStream_t st = ctx->stream;
     double *dots = ctx->ws.dev_scalars + 8;
     timing_begin(ctx, FVK_STAGE_ORTHO);
@@ -878,6 +939,8 @@ fvk_status arnoldi_step_lagged(fvk_ctx *ctx, const double *base, double *V, size
     CHECK_LAUNCH(ctx);
     return FVK_OK;
 }
+
+extern "C" {
 
 fvk_status arnoldi_finish(fvk_ctx *ctx, double *V, size_t ldv, int j, double *H, int ldh) {
     if (!ctx || !V || !H || j < 0 || (j > 0 && ldh < j)) return FVK_EINVAL;

@@ -103,6 +103,7 @@ struct Workspace {
     int ring_n = 0;
     int *dev_counters = nullptr;    // [0] async calls above tolerance, [1] block counter
     double *div_slots = nullptr;    // [0] max |D v| of the last pass, [1] running max (async)
+    double *zeros = nullptr;        // max(nx, ny, nz) zeros (plane-wise solves)
     double *host_pinned = nullptr;  // pinned host staging for small reads
     size_t host_pinned_len = 0;
 };
@@ -185,6 +186,20 @@ bool noalloc_prepare(std::string *err);
 void tpf_solve(fvk_ctx *ctx, const double *b, double *phi, bool fp32, hipStream_t st,
                const double *vel = nullptr, int win = 0);
 bool tpf_fuses_div(const fvk_ctx *ctx);
+// phi = L_bc^+ b in every plane normal to axis `normal` (b, c the other two
+// axes), FP64; the constant mode of each plane gets coefficient 0
+void tpf_solve_plane(fvk_ctx *ctx, const double *b, double *phi, int normal, hipStream_t st);
+
+// ---- plane projections (kernels_psi.hip)
+// div = D_bc v at the cells (in-plane faces only; wall faces read as 0)
+void launch_div_plane(const Geo &g, const double *v, double *div, int normal, hipStream_t st);
+// vout = in-plane components of vin minus G_bc phi at interior faces, 0 elsewhere
+// (normal component 0); vout may be vin
+void launch_correct_plane(const Geo &g, const double *vin, const double *phi, double *vout,
+                          int normal, hipStream_t st);
+// psi (one stored field) on the edges along `normal`: v = curl(psi e_normal),
+// 0 on the walls, by integration of the first in-plane component
+void launch_psi_lines(const Geo &g, const double *vp, double *psi, int normal, hipStream_t st);
 
 // ---- BLAS-like kernels (kernels_blas.hip)
 int multidot_blocks(size_t n);
@@ -208,6 +223,9 @@ void launch_absmax(const double *x, size_t n, double *partials, int nblk, hipStr
 void launch_scale_inv_sqrt(double *w, const double *nrm2, size_t n, hipStream_t st);
 void launch_axpby(double *y, double a, const double *x, double b, size_t n, hipStream_t st);
 void launch_fill(double *y, double v, size_t n, hipStream_t st);
+// z = a x + b y + c z (z may alias neither x nor y)
+void launch_lincomb3(double *z, double a, const double *x, double b, const double *y, double c,
+                     size_t n, hipStream_t st);
 void launch_copy(double *dst, const double *src, size_t n, hipStream_t st);
 void launch_scale(double *w, double alpha, size_t n, hipStream_t st);
 

@@ -294,6 +294,13 @@ __global__ void k_axpby(double *__restrict__ y, double a, const double *__restri
     y[r] = a * x[r] + b * y[r];
 }
 
+__global__ void k_lincomb3(double *__restrict__ z, double a, const double *__restrict__ x,
+                           double b, const double *__restrict__ y, double c, size_t n) {
+    const size_t r = size_t(blockIdx.x) * NT + threadIdx.x;
+    if (r >= n) return;
+    z[r] = a * x[r] + b * y[r] + c * z[r];
+}
+
 __global__ void k_fill(double *__restrict__ y, double v, size_t n) {
     const size_t r = size_t(blockIdx.x) * NT + threadIdx.x;
     if (r < n) y[r] = v;
@@ -387,6 +394,11 @@ void launch_scale_inv_sqrt(double *w, const double *nrm2, size_t n, hipStream_t 
 
 void launch_axpby(double *y, double a, const double *x, double b, size_t n, hipStream_t st) {
     k_axpby<<<nblk1(n), NT, 0, st>>>(y, a, x, b, n);
+}
+
+void launch_lincomb3(double *z, double a, const double *x, double b, const double *y, double c,
+                     size_t n, hipStream_t st) {
+    k_lincomb3<<<nblk1(n), NT, 0, st>>>(z, a, x, b, y, c, n);
 }
 
 void launch_fill(double *y, double v, size_t n, hipStream_t st) {

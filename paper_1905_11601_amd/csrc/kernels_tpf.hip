@@ -79,7 +79,11 @@ __device__ __forceinline__ long col_addr(const AxisView &v, int c) {
 // accumulators).  K is staged through LDS in chunks of KC.  CONTIG: the
 // transform index is the unit-stride one (x axis), so X tiles are loaded with
 // consecutive threads along K.  SCALE: multiply each output by
-// 1 / (lamR[row] + lam0[c0] + lam1[c1]) (0 for the all-constant mode).
+// 1 / (lamR[row] + lam0[c0] + lam1[c1]), 0 where that sum vanishes: the
+// eigenvalues are <= 0 with exactly 0 only for the constant mode of an axis,
+// so these are the singular modes (the all-constant one of the 3D solve; one
+// per plane when an axis's eigenvalues are replaced by zeros, as in the
+// plane-wise 2D solves).
 template <typename Tc, typename Tin, typename Tout, bool CONTIG, bool SCALE>
 __global__ __launch_bounds__(NT) void k_axis(const Tc *__restrict__ M, AxisView v,
                                              const Tin *__restrict__ X, Tout *__restrict__ Y,
@@ -139,7 +143,7 @@ __global__ __launch_bounds__(NT) void k_axis(const Tc *__restrict__ M, AxisView 
             if (SCALE) {
                 const int ch = col_hi(v, col);
                 const Tc l = lamR[row] + lam0[col - ch * v.n0] + lam1[ch];
-                val = (row == 0 && col == 0) ? Tc(0) : val / l;
+                val = l == Tc(0) ? Tc(0) : val / l;   // singular (constant) modes -> 0
             }
             Y[ca + long(row) * v.sb] = Tout(val);
         }
@@ -376,7 +380,10 @@ __global__ __launch_bounds__(64 * NW) void k_axis_sym(const Tc *__restrict__ M, 
                 Tc ve = pe, vo = po;
                 if (SCALE) {
                     const Tc l01 = s01[SCALE ? cp : 0][r];
-                    ve = (t == 0 && pp == 0) ? Tc(0) : pe * recip(sre[SCALE ? cp : 0][r] + l01);
+                    // the eigenvalue sum vanishes exactly on the singular
+                    // (all-constant) modes: mapped to 0
+                    const Tc den = sre[SCALE ? cp : 0][r] + l01;
+                    ve = den == Tc(0) ? Tc(0) : pe * recip(den);
                     if (t < no) vo = po * recip(sro[SCALE ? cp : 0][r] + l01);
                 }
                 Y[base + long(t) * v.sb] = Tout(ve);
@@ -599,7 +606,8 @@ __global__ __launch_bounds__(64 * NW) void k_axis_res(const Tc *__restrict__ M, 
                     if (SCALE) {
                         const int ph = col_hi(v, pp);
                     const Tc l01 = lam0[pp - ph * v.n0] + lam1[ph];
-                        ve = (t == 0 && pp == 0) ? Tc(0) : pe * recip(lamR[t] + l01);
+                        const Tc den = lamR[t] + l01;
+                        ve = den == Tc(0) ? Tc(0) : pe * recip(den);
                         if (t < no) vo = po * recip(lamR[ne + t] + l01);
                     }
                     Y[base + long(t) * v.sb] = Tout(ve);
@@ -714,7 +722,58 @@ void tpf_typed(fvk_ctx *ctx, const double *b, double *phi, const AxisFactors<Tc>
     timing_end(ctx, FVK_STAGE_TRANSFORM, vel ? 5 : 6);
 }
 
+// The plane-wise solve L_bc^+ b of the planes normal to axis `normal`: the
+// transforms of the two in-plane axes only, the normal axis's eigenvalues
+// replaced by zeros in the scaling (so each plane's constant mode is the
+// singular one, mapped to 0).  FP64.
+void tpf_plane_typed(fvk_ctx *ctx, const double *b, double *phi, const AxisFactors<double> *F,
+                     const double *zeros, int normal, hipStream_t st) {
+    const int nx = ctx->n[0], ny = ctx->n[1], nz = ctx->n[2];
+    const long pl = long(nx) * ny;
+    const AxisView vx = axis_view(nx, 1, ny, nx, pl, ny * nz);
+    const AxisView vy = axis_view(ny, nx, nx, 1, pl, nx * nz);
+    const AxisView vz = axis_view(nz, pl, nx, 1, nx, nx * ny);
+    double *t0 = static_cast<double *>(ctx->ws.tb0);
+    double *t1 = static_cast<double *>(ctx->ws.tb1);
+    const double *none = nullptr;
+    if (normal == 0) {   // planes x = const: axes y, z
+        axis_step<double, double, double, false, false, true>(F[1], vy, b, t0, none, none, none, st);
+        axis_step<double, double, double, false, true, true>(F[2], vz, t0, t1, F[2].lam, zeros,
+                                                             F[1].lam, st);
+        axis_step<double, double, double, false, false, false>(F[2], vz, t1, t0, none, none, none,
+                                                               st);
+        axis_step<double, double, double, false, false, false>(F[1], vy, t0, phi, none, none, none,
+                                                               st);
+    } else if (normal == 1) {   // planes y = const: axes x, z
+        axis_step<double, double, double, true, false, true>(F[0], vx, b, t0, none, none, none, st);
+        axis_step<double, double, double, false, true, true>(F[2], vz, t0, t1, F[2].lam, F[0].lam,
+                                                             zeros, st);
+        axis_step<double, double, double, false, false, false>(F[2], vz, t1, t0, none, none, none,
+                                                               st);
+        axis_step<double, double, double, true, false, false>(F[0], vx, t0, phi, none, none, none,
+                                                              st);
+    } else {   // planes z = const: axes x, y (scaling on the y step: columns (k, i))
+        axis_step<double, double, double, true, false, true>(F[0], vx, b, t0, none, none, none, st);
+        axis_step<double, double, double, false, true, true>(F[1], vy, t0, t1, F[1].lam, F[0].lam,
+                                                             zeros, st);
+        axis_step<double, double, double, false, false, false>(F[1], vy, t1, t0, none, none, none,
+                                                               st);
+        axis_step<double, double, double, true, false, false>(F[0], vx, t0, phi, none, none, none,
+                                                              st);
+    }
+}
+
 }  // namespace
+
+void tpf_solve_plane(fvk_ctx *ctx, const double *b, double *phi, int normal, hipStream_t st) {
+    const Workspace &w = ctx->ws;
+    AxisFactors<double> F[3];
+    for (int a = 0; a < 3; ++a) {
+        const bool sym = ctx->n[a] <= kSymMax;
+        F[a] = {sym ? w.Ah[a] : w.Einv[a], sym ? w.Bh[a] : w.E[a], sym ? w.lamp[a] : w.lam[a], sym};
+    }
+    tpf_plane_typed(ctx, b, phi, F, w.zeros, normal, st);
+}
 
 bool tpf_fuses_div(const fvk_ctx *ctx) {
     // the streaming even/odd kernel, up to 256 cells along x (for 193..256

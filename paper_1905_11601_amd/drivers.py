@@ -52,6 +52,90 @@ def steady_state(ctx, base, Gr, Gr_start=1e3, factor=3.3, newton_opts=None, log=
             g_next = min(Gr, g_done * step)
 
 
+def _interp_axis(a, dim, xc, xf):
+    """Linear interpolation of array a along dimension dim from the increasing
+    coordinates xc to xf (both inside the same interval [xc[0], xc[-1]])."""
+    idx = np.clip(np.searchsorted(xc, xf, side="right") - 1, 0, len(xc) - 2)
+    w = (xf - xc[idx]) / (xc[idx + 1] - xc[idx])
+    shape = [1] * a.ndim
+    shape[dim] = len(xf)
+    w = w.reshape(shape)
+    return np.take(a, idx, axis=dim) * (1.0 - w) + np.take(a, idx + 1, axis=dim) * w
+
+
+def prolong_fields(coarse, fc, cc, ff, cf):
+    """A 4-field state on a coarse staggered grid interpolated (trilinear,
+    field by field at its own nodes) to a fine grid of the same kind.
+
+    coarse: (4, nz+2, ny+2, nx+2) array; fc, cc / ff, cf: per-axis (x, y, z)
+    face coordinates f[0..n] and centres c[0..n+1] (wall nodes included) of
+    the coarse / fine grid.  Velocity component a lives on the a-faces along
+    axis a (stored indices 0..n; index n+1 is padding and stays 0) and on the
+    centres along the other axes; T on the centres."""
+    nzf, nyf, nxf = (len(ff[a]) - 1 for a in (2, 1, 0))
+    out = np.zeros((4, nzf + 2, nyf + 2, nxf + 2))
+    for fld in range(4):
+        a = np.asarray(coarse[fld])
+        sl_c, sl_f = [], []
+        for axis in (2, 1, 0):               # array dims (z, y, x)
+            own = fld == axis
+            nc, nf = len(fc[axis]) - 1, len(ff[axis]) - 1
+            sl_c.append(slice(0, nc + 1) if own else slice(0, nc + 2))
+            sl_f.append(slice(0, nf + 1) if own else slice(0, nf + 2))
+        a = a[tuple(sl_c)]
+        for dim, axis in enumerate((2, 1, 0)):
+            own = fld == axis
+            xc = np.asarray(fc[axis] if own else cc[axis])
+            xf = np.asarray(ff[axis] if own else cf[axis])
+            a = _interp_axis(a, dim, xc, xf)
+        out[fld][tuple(sl_f)] = a
+    return out
+
+
+def prolong_base(ctx_coarse, base_coarse, ctx_fine):
+    """A steady state of ctx_coarse as the start of the Newton iteration on
+    the finer grid of ctx_fine: interpolated to the fine nodes, velocity
+    projected onto the divergence-free no-slip subspace by the library (one
+    SIMPLE pass), temperature wall nodes reset to the boundary values of
+    eqs (4)-(7).  Returns a fine-grid CUDA tensor."""
+    import torch
+    from . import inputs
+    fc, cc, _ = ctx_coarse.coords()
+    ff, cf, _ = ctx_fine.coords()
+    U = prolong_fields(base_coarse.cpu().numpy(), fc, cc, ff, cf)
+    U[3] = inputs._theta_walls(U[3], np.asarray(cf[0]), ctx_fine.span_bc)
+    Ud = torch.as_tensor(U).cuda()
+    P = ctx_fine.project(Ud)
+    Ud[:3] = P[:3]
+    return Ud
+
+
+def steady_state_refined(ctx, n_coarse, Gr, log=None, newton_opts=None, coarse_opts=None):
+    """Newton steady state at Gr on ctx's grid, started from the steady state
+    of the same problem on a coarser grid (n_coarse cells per axis, reached by
+    continuation in Gr there) interpolated by ``prolong_base``: the fine grid
+    then needs only the last Newton iterations.  Returns (base, report of the
+    fine Newton iteration, coarse stages)."""
+    import torch
+    from . import Ctx, inputs
+    cctx = Ctx(n_coarse, grid=ctx.grid_kind, s=ctx.s, span_bc=ctx.span_bc, Gr=Gr, Pr=ctx.Pr,
+               device=ctx.device)
+    _, c, _ = cctx.coords()
+    Uc = torch.as_tensor(inputs.conduction_state(c, ctx.span_bc)).cuda()
+    stages = steady_state(cctx, Uc, Gr, newton_opts=coarse_opts, log=log)
+    U = prolong_base(cctx, Uc, ctx)
+    del Uc
+    cctx.close()
+    ctx.set_params(Gr)
+    opts = dict(tol=1e-10, gmres_m=100, lin_tol=1e-10, max_newton=10)
+    opts.update(newton_opts or {})
+    rep = ctx.newton_step(U, **opts)
+    if log:
+        log(f"refined Newton on {ctx.n}: status {rep['status']} its {rep['newton_its']} "
+            f"res {rep['res_before']:.2e} -> {rep['res_after']:.2e}")
+    return U, rep, stages
+
+
 def base_flow_sensitivity(ctx, base, lin_opts=None):
     """U' = dU/dGr at a steady state: A U' = -P dF/dGr, where dF/dGr is the
     residual's explicit Gr dependence (nu' Lap U, kappa' Lap Theta)."""

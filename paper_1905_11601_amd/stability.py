@@ -26,7 +26,11 @@ def main(argv=None):
     ap.add_argument("--bc", choices=("CC", "AA"), default="CC", help="spanwise walls")
     ap.add_argument("--gr", type=float, default=1e6)
     ap.add_argument("--pr", type=float, default=0.71)
-    ap.add_argument("--base", choices=("synthetic", "newton"), default="synthetic")
+    ap.add_argument("--base", choices=("synthetic", "newton", "refined"), default="synthetic",
+                    help="newton: steady state by continuation in Gr on this grid; refined: "
+                         "continuation on a --coarse grid, interpolated, Newton on this grid")
+    ap.add_argument("--coarse", type=int, default=64, help="coarse grid of --base refined")
+    ap.add_argument("--newton-tol", type=float, default=1e-10)
     ap.add_argument("--k", type=int, default=4, help="eigenvalues wanted")
     ap.add_argument("--m", type=int, default=100, help="Krylov dimension")
     ap.add_argument("--keep", type=int, default=None,
@@ -37,13 +41,15 @@ def main(argv=None):
                     help="both: FP64, then mixed precision on the same base flow, with the "
                          "eigenvalue differences")
     ap.add_argument("--seed", type=int, default=5000, help="seed of the start vector")
+    ap.add_argument("--chebyshev", type=int, default=0, metavar="DEGREE",
+                    help="Krylov-Schur on the Chebyshev filter of this degree (0: plain)")
     args = ap.parse_args(argv)
 
     import torch
     import paper_1905_11601_amd as fvk
     from paper_1905_11601_amd import inputs
-    from paper_1905_11601_amd.drivers import steady_state
-    from paper_1905_11601_amd.eigs import krylov_schur, ritz_residual
+    from paper_1905_11601_amd.drivers import steady_state, steady_state_refined
+    from paper_1905_11601_amd.eigs import krylov_schur, krylov_schur_chebyshev, ritz_residual
 
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
@@ -55,9 +61,15 @@ def main(argv=None):
     t0 = time.perf_counter()
     if args.base == "synthetic":
         base = torch.as_tensor(inputs.synthetic_base(f, c, h, bc)).cuda()
-    else:
+    elif args.base == "newton":
         base = torch.as_tensor(inputs.conduction_state(c, bc)).cuda()
-        steady_state(ctx, base, args.gr, log=log)
+        steady_state(ctx, base, args.gr, newton_opts=dict(tol=args.newton_tol), log=log)
+    else:
+        base, rep, _ = steady_state_refined(ctx, args.coarse, args.gr, log=log,
+                                            newton_opts=dict(tol=args.newton_tol),
+                                            coarse_opts=dict(tol=max(args.newton_tol, 1e-9)))
+        if rep["status"] != 0:
+            log(f"refined Newton did not reach the tolerance: {rep}")
     t_base = time.perf_counter() - t0
     ctx.set_params(args.gr, args.pr)
     v0 = ctx.project(torch.as_tensor(inputs.random_fields(ctx.n, args.seed)).cuda())
@@ -67,23 +79,29 @@ def main(argv=None):
         ctx.set_precision(fvk.MIXED if prec == "mixed" else fvk.FP64)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        r = krylov_schur(ctx, base, k=args.k, m=args.m, v0=v0, tol=args.tol,
-                         max_restarts=args.max_restarts, keep=args.keep,
-                         log=lambda s: log(s) if int(s.split()[1].rstrip(":")) % every == 0
-                         else None)
+        if args.chebyshev > 0:
+            r = krylov_schur_chebyshev(ctx, base, k=args.k, m=args.m, v0=v0, tol=args.tol,
+                                       degree=args.chebyshev, max_restarts=args.max_restarts,
+                                       keep=args.keep, log=log)
+        else:
+            r = krylov_schur(ctx, base, k=args.k, m=args.m, v0=v0, tol=args.tol,
+                             max_restarts=args.max_restarts, keep=args.keep,
+                             log=lambda s: log(s) if int(s.split()[1].rstrip(":")) % every == 0
+                             else None)
         torch.cuda.synchronize()
         t_eig = time.perf_counter() - t1
         res = [ritz_residual(ctx, base, r.lam[q], r.X[q]) for q in range(len(r.lam))]
         return {
             "precision": prec, "converged": r.converged, "restarts": r.restarts,
-            "krylov_vectors": r.nvec,
+            "krylov_vectors": r.nvec, "orthogonalisation_steps": getattr(r, "orth_steps", r.nvec),
+            "ellipse": getattr(r, "ellipse", None),
             "eigenvalues": [[float(np.real(v)), float(np.imag(v))] for v in r.lam],
             "ritz_residuals": res, "eigen_seconds": t_eig}, r
 
     out = {
         "grid": [args.n] * 3, "grid_kind": args.grid, "s": args.s, "span_bc": args.bc,
         "Gr": args.gr, "Pr": args.pr, "base": args.base, "k": args.k, "m": args.m,
-        "keep": args.keep, "tol": args.tol, "base_seconds": t_base,
+        "keep": args.keep, "tol": args.tol, "base_seconds": t_base, "chebyshev": args.chebyshev,
     }
     if args.prec == "both":
         o64, r64 = solve("fp64")

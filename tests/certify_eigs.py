@@ -54,7 +54,8 @@ def main(argv=None):
     ap.add_argument("--bc", choices=("CC", "AA"), default="CC")
     ap.add_argument("--gr", type=float, default=1e6)
     ap.add_argument("--pr", type=float, default=0.71)
-    ap.add_argument("--base", choices=("synthetic", "newton"), default="synthetic")
+    ap.add_argument("--base", choices=("synthetic", "newton", "refined"), default="synthetic")
+    ap.add_argument("--coarse", type=int, default=64, help="coarse grid of --base refined")
     ap.add_argument("--newton-tol", type=float, default=1e-9)
     ap.add_argument("--k", type=int, default=4)
     ap.add_argument("--m", type=int, default=100)
@@ -69,7 +70,7 @@ def main(argv=None):
     import torch
     import paper_1905_11601_amd as fvk
     from paper_1905_11601_amd import inputs
-    from paper_1905_11601_amd.drivers import steady_state
+    from paper_1905_11601_amd.drivers import steady_state, steady_state_refined
     from paper_1905_11601_amd.eigs import krylov_schur, ritz_residual
     from oracle import ops
     from oracle.grid import Grid, TANH
@@ -93,14 +94,27 @@ def main(argv=None):
         base_info = {"base": "synthetic"}
     else:
         c = tuple(a.c for a in g.ax)
-        Ud = torch.as_tensor(inputs.conduction_state(c, bc)).cuda()
-        stages = steady_state(ctx, Ud, args.gr, newton_opts=dict(tol=args.newton_tol), log=log)
+        if args.base == "newton":
+            Ud = torch.as_tensor(inputs.conduction_state(c, bc)).cuda()
+            stages = steady_state(ctx, Ud, args.gr, newton_opts=dict(tol=args.newton_tol),
+                                  log=log)
+            fine = None
+        else:
+            Ud, fine, stages = steady_state_refined(ctx, args.coarse, args.gr, log=log,
+                                                    newton_opts=dict(tol=args.newton_tol),
+                                                    coarse_opts=dict(tol=1e-9))
         U = Ud.cpu()
         res_ora = float(orc.residual(U, project=True).abs().max())
-        base_info = {"base": "newton", "newton_stages": [[s_[0], s_[1]["newton_its"]]
-                                                         for s_ in stages],
+        base_info = {"base": args.base, "newton_stages": [[s_[0], s_[1]["newton_its"]]
+                                                          for s_ in stages],
                      "newton_seconds": time.perf_counter() - t0,
                      "oracle_max_projected_residual": res_ora}
+        if fine is not None:
+            base_info["coarse_grid"] = args.coarse
+            base_info["fine_newton"] = {k: fine[k] for k in ("status", "newton_its",
+                                                              "res_before", "res_after",
+                                                              "gmres_cycles", "bicgstab_its",
+                                                              "krylov_vecs")}
         log(f"steady state: oracle max|P F| = {res_ora:.3e}")
     v0 = ctx.project(torch.as_tensor(inputs.random_fields(ctx.n, 5000)).cuda())
     out = {"grid": [n] * 3, "grid_kind": "tanh", "s": 1.5, "span_bc": args.bc, "Gr": args.gr,

@@ -335,3 +335,26 @@ def test_term_switches(fvk, name, mask, bc):
     ctx.set_terms(fvk.TERMS_ALL)
     orc.terms = (1 << 9) - 1
     assert rel_err(ctx.simple_krylov_vec(dev(U), dev(x)), orc.krylov_vec(U, x)) < 1e-10
+
+
+PSI_CASES = [((12, 10, 14), TANH, 1.5), ((9, 13, 11), SINE, 0.12), ((70, 40, 55), TANH, 1.5)]
+
+
+@pytest.mark.parametrize("n,kind,s", PSI_CASES, ids=["12x10x14", "9x13x11-sine", "70x40x55"])
+@pytest.mark.parametrize("axis", [0, 1, 2], ids=["x", "y", "z"])
+def test_psi_projection(fvk, n, kind, s, axis):
+    """Divergence-free projections onto the coordinate planes and their
+    vector potentials (fvk_psi_projection) against the oracle, for a raw
+    random field and for the synthetic base flow, in place too."""
+    from oracle.psi import project_plane, psi_plane
+    print(f"case psi n={n} axis={axis}", flush=True)
+    g, orc, ctx = setup(n, kind, s, 0)
+    for x in (krylov_input(g, orc, 2300, project=False), base(g, 0)):
+        ref, _ = project_plane(g, [x[0], x[1], x[2]], axis)
+        pref = psi_plane(g, ref, axis)
+        vp, psi = ctx.psi_projection(dev(x), axis)
+        assert rel_err(vp, torch.stack(ref)) < TOL
+        assert rel_err(psi, pref) < TOL
+    xd = dev(x)
+    ctx.lib.fvk_psi_projection(ctx.h, fvk._ptr(xd), axis, fvk._ptr(xd), None)   # in place
+    assert rel_err(xd[:3], torch.stack(ref)) < TOL

@@ -234,3 +234,32 @@ def test_jacobian_commutes_with_symmetries(bc, S):
     lhs = ops.jacvec(g, prm, base, S(g, x))
     rhs = S(g, ops.jacvec(g, prm, base, x))
     assert float((lhs - rhs).abs().max()) < 1e-12 * float(rhs.abs().max())
+
+
+def test_prolongation_is_exact_for_trilinear_fields():
+    """The coarse-to-fine interpolation of the Newton driver (each staggered
+    field at its own nodes) reproduces any field that is trilinear in the
+    physical coordinates exactly, on stretched grids of different sizes."""
+    import numpy as np
+    from paper_1905_11601_amd.drivers import prolong_fields
+    gc, gf = Grid(6, 5, 7, kind=TANH, s=1.5), Grid(11, 9, 13, kind=TANH, s=1.5)
+
+    def fields(g):
+        out = np.zeros((4,) + g.shape)
+        for fld in range(4):
+            coords = []
+            for axis in range(3):
+                own = fld == axis
+                coords.append(np.asarray(g.ax[axis].f if own else g.ax[axis].c))
+            x, y, z = np.meshgrid(*coords, indexing="ij")
+            val = (1 + 2 * x - 3 * y + 0.5 * z + x * y - 2 * y * z + 0.25 * x * y * z).transpose(2, 1, 0)
+            sl = tuple(slice(0, len(coords[a])) for a in (2, 1, 0))
+            out[fld][sl] = val
+        return out
+
+    fc = tuple(a.f for a in gc.ax)
+    cc = tuple(a.c for a in gc.ax)
+    ff = tuple(a.f for a in gf.ax)
+    cf = tuple(a.c for a in gf.ax)
+    got = prolong_fields(fields(gc), fc, cc, ff, cf)
+    assert np.max(np.abs(got - fields(gf))) < 1e-12
