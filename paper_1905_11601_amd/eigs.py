@@ -313,27 +313,35 @@ class _ChebOp:
 
 def krylov_schur_chebyshev(ctx, base, k, m, v0, degree=10, tol=1e-10, max_restarts=200,
                            transpose=False, warm_restarts=3, extra=None, log=None,
-                           shift="auto", keep=None):
+                           shift="auto", keep=None, refit_every=40):
     """k rightmost eigenvalues of A (A^T) by Krylov-Schur on the Chebyshev
     filter M = p_degree(A + s P) (see the notes above).
 
     The filter's ellipse is fitted to the unwanted Ritz values of
     ``warm_restarts`` plain Krylov-Schur cycles (Krylov dimension m) from v0;
-    the k + extra (default k) rightmost Ritz values are the wanted set.  The
+    the k + extra (default max(2, k // 2)) rightmost Ritz values are the
+    wanted set.  The
     filtered iteration starts from the sum of the warm-up Ritz vectors of the
-    wanted set, targets the largest |p(theta)|, and after each cycle in which
-    its wanted Ritz values converge (relative residual of M below tol_m) the
-    eigenpairs of A are extracted by Rayleigh-Ritz on that invariant subspace
-    (one Krylov vector per basis vector); it stops when the k rightmost have
-    explicit residuals || A x - lam x || / || x || below tol, else tightens
-    tol_m tenfold and goes on.  Returns an EigResult (res = the explicit
+    wanted set and targets the largest |p(theta)|.  When its wanted Ritz
+    values converge (relative residual of M below tol_m), and every
+    ``refit_every`` restarts in any case, the eigenpairs of A are extracted by
+    Rayleigh-Ritz on the dominant invariant subspace of M (one Krylov vector
+    per basis vector); it stops when the k rightmost have explicit residuals
+    || A x - lam x || / || x || below tol.  Otherwise the extracted values
+    outside the wanted set join the unwanted ones and the ellipse is refitted
+    (adaptive Chebyshev acceleration): a short warm-up can miss unwanted
+    eigenvalues with large imaginary parts near the right end of the
+    spectrum, which a too-flat ellipse then amplifies; once seen they are
+    enclosed, and the iteration restarts from the current Ritz vectors of the
+    wanted set.  If the fit does not change, tol_m is tightened tenfold.  Returns an EigResult (res = the explicit
     residuals; nvec counts every Krylov vector, filter and extraction
     included; .orth_steps the Arnoldi orthogonalisation steps)."""
     import torch
-    extra = k if extra is None else int(extra)
+    extra = max(2, k // 2) if extra is None else int(extra)
     nw = k + extra
-    if not (0 < nw < m - 1):
-        raise ValueError("need 0 < k + extra < m - 1")
+    if not (0 < k and 2 * (nw + 1) <= m):
+        raise ValueError("need 2 (k + extra + 1) <= m (the warm-up Ritz vectors of the wanted "
+                         "set, a conjugate pair included, fill at most half the basis)")
     r0 = krylov_schur(ctx, base, nw, m, v0, tol=tol, max_restarts=warm_restarts,
                       transpose=transpose, vectors=True, shift=shift, keep=keep)
     sigma = r0.shift
@@ -376,7 +384,11 @@ def krylov_schur_chebyshev(ctx, base, k, m, v0, degree=10, tol=1e-10, max_restar
         orth = 0
         res_a = lam_a = Xa = None
         converged = False
+        pool = np.asarray(theta[min(len(theta), nw):])      # unwanted Ritz values seen so far
+        best = None                                         # (worst residual, lam, X, res)
+        since = 0                                           # restarts since the last (re)start
         for restart in range(max_restarts + 1):
+            since += 1
             for j in range(p, m):
                 op.apply(V[j], V[j + 1])
                 ctx.arnoldi_step_lagged_applied(V, j, H)
@@ -393,7 +405,8 @@ def krylov_schur_chebyshev(ctx, base, k, m, v0, degree=10, tol=1e-10, max_restar
             if log and restart % 10 == 0:
                 log(f"chebyshev restart {restart}: nvec {nvec}, |mu_1| {abs(mu[0]):.4g}, "
                     f"res_M {res_m[:nw].max():.2e}")
-            if np.all(res_m[:nw] < tol_m) or restart == max_restarts:
+            m_conv = bool(np.all(res_m[:nw] < tol_m))
+            if m_conv or restart == max_restarts or since % refit_every == 0:
                 # Rayleigh-Ritz with A_s on the wanted invariant subspace of M
                 S, Q, sdim = sla.schur(Hm, output="real",
                                        sort=lambda re, im: np.hypot(re, im) >= thr_w * (1 - 1e-12))
@@ -402,13 +415,52 @@ def krylov_schur_chebyshev(ctx, base, k, m, v0, degree=10, tol=1e-10, max_restar
                                                       transpose)
                 nvec += nmv
                 good = len(lam_a) >= k and np.all(res_a[:k] < tol)
+                worst = float(res_a[:k].max()) if len(lam_a) >= k else np.inf
                 if log:
                     log(f"chebyshev extraction at restart {restart}: {lam_a[:k]} "
-                        f"residuals {res_a[:k].max():.2e}")
+                        f"residuals {worst:.2e}")
+                if best is None or worst < best[0]:
+                    best = (worst, lam_a, Xa, res_a)
                 if good or restart == max_restarts:
                     converged = bool(good)
+                    if not good:    # the best extraction seen, not the last one
+                        _, lam_a, Xa, res_a = best
                     break
-                tol_m = tol_m / 10.0
+                if worst < 1e-3:
+                    # converging on the wanted set: keep the filter
+                    if m_conv:
+                        tol_m = tol_m / 10.0
+                    continue_refit = False
+                else:
+                    continue_refit = True
+                # refit the ellipse to every unwanted value seen so far
+                th_x = np.asarray(lam_a) + sigma
+                if not continue_refit:
+                    th_x = th_x[:0]
+                pool = np.concatenate([pool, th_x[nw:]])
+                allv = np.concatenate([th_x[:nw], pool])
+                allv = allv[_order(allv)]
+                nfit = fit_ellipse(allv, min(nw, len(th_x))) if continue_refit else None
+                if nfit is not None and (abs(nfit[3] - b) > 1e-3 * max(b, 1e-300)
+                                         or abs(nfit[0] - c) > 1e-6 * abs(c)):
+                    c, e, a, b, rate = nfit
+                    op.coeffs = _cheb_coeffs(c, e, float(allv[0].real), degree)
+                    if log:
+                        log(f"chebyshev refit at restart {restart}: ellipse centre {c - sigma:.6g} "
+                            f"semi-axes {a:.4g} x {b:.4g}, per-degree damping {rate:.6f}")
+                    # restart from the current Ritz vectors of the wanted set
+                    V[0].zero_()
+                    XRa, XIa = Xa.real.contiguous(), Xa.imag.contiguous()
+                    for i in range(min(nw, XRa.shape[0])):
+                        ctx.lincomb3(V[0], 1.0, XRa[i], 1.0, XIa[i], 1.0)
+                    del XRa, XIa
+                    ctx.normalize(V[0])
+                    H[:] = 0.0
+                    p = 0
+                    since = 0
+                    continue
+                if m_conv and continue_refit:
+                    tol_m = tol_m / 10.0
             # Krylov-Schur truncation on M: keep the largest |mu|
             thr = np.abs(mu[kept - 1])
             S, Q, sdim = sla.schur(Hm, output="real",
@@ -442,8 +494,11 @@ def _rayleigh_ritz(ctx, base, V, Qs, sigma, m, transpose):
     by (-Re, -Im), unit X (complex rows), residuals, Krylov vectors used)."""
     import torch
     q = Qs.shape[1]
-    ctx.basis_rotate(V, Qs)                      # V[:q] = B
-    Bm = V[:q].clone()
+    # B = V[:m] Qs in its own buffer (one pass over the basis per column): the
+    # basis itself must stay intact for the iteration to continue
+    Bm = torch.zeros((q, V.shape[1]), dtype=V.dtype, device=V.device)
+    for i in range(q):
+        ctx.multiaxpy(Bm[i], 0.0, V[:m], np.ascontiguousarray(Qs[:, i]))
     C = torch.empty_like(Bm)
     for i in range(q):
         ctx.simple_krylov_vec(base, Bm[i].reshape(ctx.shape4), out=C[i].reshape(ctx.shape4),

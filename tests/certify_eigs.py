@@ -63,6 +63,8 @@ def main(argv=None):
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-restarts", type=int, default=3000)
     ap.add_argument("--prec", choices=("fp64", "mixed", "both"), default="both")
+    ap.add_argument("--chebyshev", type=int, default=0, metavar="DEGREE",
+                    help="Krylov-Schur on the Chebyshev filter of this degree (0: plain)")
     ap.add_argument("--threads", type=int, default=16, help="oracle (torch CPU) threads")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
@@ -71,7 +73,7 @@ def main(argv=None):
     import paper_1905_11601_amd as fvk
     from paper_1905_11601_amd import inputs
     from paper_1905_11601_amd.drivers import steady_state, steady_state_refined
-    from paper_1905_11601_amd.eigs import krylov_schur, ritz_residual
+    from paper_1905_11601_amd.eigs import krylov_schur, krylov_schur_chebyshev, ritz_residual
     from oracle import ops
     from oracle.grid import Grid, TANH
     from oracle.krylov import Oracle
@@ -102,7 +104,7 @@ def main(argv=None):
         else:
             Ud, fine, stages = steady_state_refined(ctx, args.coarse, args.gr, log=log,
                                                     newton_opts=dict(tol=args.newton_tol),
-                                                    coarse_opts=dict(tol=1e-9))
+                                                    coarse_opts=dict(tol=args.newton_tol))
         U = Ud.cpu()
         res_ora = float(orc.residual(U, project=True).abs().max())
         base_info = {"base": args.base, "newton_stages": [[s_[0], s_[1]["newton_its"]]
@@ -118,7 +120,8 @@ def main(argv=None):
         log(f"steady state: oracle max|P F| = {res_ora:.3e}")
     v0 = ctx.project(torch.as_tensor(inputs.random_fields(ctx.n, 5000)).cuda())
     out = {"grid": [n] * 3, "grid_kind": "tanh", "s": 1.5, "span_bc": args.bc, "Gr": args.gr,
-           "Pr": args.pr, "k": args.k, "m": args.m, "keep": args.keep, "tol": args.tol}
+           "Pr": args.pr, "k": args.k, "m": args.m, "keep": args.keep, "tol": args.tol,
+           "chebyshev": args.chebyshev}
     out.update(base_info)
     lams = {}
     precs = ["fp64", "mixed"] if args.prec == "both" else [args.prec]
@@ -127,10 +130,18 @@ def main(argv=None):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         every = max(1, args.max_restarts // 60)
-        r = krylov_schur(ctx, Ud, k=args.k, m=args.m, v0=v0, tol=args.tol,
-                         max_restarts=args.max_restarts, keep=args.keep,
-                         log=lambda s_: log(s_) if int(s_.split()[1].rstrip(":")) % every == 0
-                         else None)
+        if args.chebyshev > 0:
+            r = krylov_schur_chebyshev(ctx, Ud, k=args.k, m=args.m, v0=v0, tol=args.tol,
+                                       degree=args.chebyshev, max_restarts=args.max_restarts,
+                                       keep=args.keep,
+                                       log=lambda s_: log(s_) if ("restart" not in s_ or
+                                                                  "00:" in s_ or
+                                                                  "extraction" in s_) else None)
+        else:
+            r = krylov_schur(ctx, Ud, k=args.k, m=args.m, v0=v0, tol=args.tol,
+                             max_restarts=args.max_restarts, keep=args.keep,
+                             log=lambda s_: log(s_) if int(s_.split()[1].rstrip(":")) % every == 0
+                             else None)
         torch.cuda.synchronize()
         t_eig = time.perf_counter() - t1
         gpu_res = [ritz_residual(ctx, Ud, r.lam[q], r.X[q]) for q in range(len(r.lam))]
@@ -140,6 +151,8 @@ def main(argv=None):
         log(f"{prec}: {r.lam} oracle residuals {ora_res} ({time.perf_counter() - t2:.1f} s)")
         lams[prec] = r.lam
         out[prec] = {"converged": r.converged, "restarts": r.restarts, "krylov_vectors": r.nvec,
+                     "orthogonalisation_steps": getattr(r, "orth_steps", r.nvec),
+                     "ellipse": getattr(r, "ellipse", None),
                      "shift": r.shift, "eigen_seconds": t_eig,
                      "eigenvalues": [[float(v.real), float(v.imag)] for v in r.lam],
                      "gpu_ritz_residuals": gpu_res, "oracle_ritz_residuals": ora_res}
