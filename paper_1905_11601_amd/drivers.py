@@ -9,7 +9,7 @@ simple_krylov_vec, arnoldi_step); these functions only sequence the calls.
 import numpy as np
 
 from .adjoint import dA_dGr_apply, _cdot, left_eigvecs
-from .eigs import krylov_schur
+from .eigs import krylov_schur, krylov_schur_chebyshev
 
 
 def steady_state(ctx, base, Gr, Gr_start=1e3, factor=3.3, newton_opts=None, log=None):
@@ -177,7 +177,7 @@ def total_dlam_dGr(ctx, base, x, y, Up):
 
 
 def critical_gr(ctx, base, Gr0, v0, seed, k=4, m=40, tol=1e-10, gr_rtol=1e-7, max_it=12,
-                log=None, terms=None):
+                log=None, terms=None, chebyshev=0, max_restarts=400, newton_opts=None):
     """Newton iteration on Gr for Re lambda_lead(Gr) = 0 (the paper's critical
     Grashof number).  ``base`` (in/out) must be a steady state at Gr0.  Each
     iteration: Newton steady state at the current Gr (from the previous one),
@@ -186,7 +186,9 @@ def critical_gr(ctx, base, Gr0, v0, seed, k=4, m=40, tol=1e-10, gr_rtol=1e-7, ma
 
     terms: coupling terms kept in the eigenvalue problem (fvk TERM_* mask, the
     mechanism experiment of Sec. 4.2); the steady states and U' always use
-    the full equations.
+    the full equations.  chebyshev: degree of the Chebyshev-accelerated
+    eigenvalue solves (0: plain Krylov-Schur); newton_opts: options of the
+    steady-state Newton iterations.
 
     The eigenvalue solves run on the shifted operator A + sigma P
     (krylov_schur's default), so a real eigenvalue crossing zero stays clear
@@ -203,17 +205,22 @@ def critical_gr(ctx, base, Gr0, v0, seed, k=4, m=40, tol=1e-10, gr_rtol=1e-7, ma
             ctx.set_terms(full)
             if it > 0:
                 # from the steady state at the previous Gr, in steps of at most 1.5x
-                steady_state(ctx, base, Gr, Gr_start=prev, factor=1.5, log=log)
+                steady_state(ctx, base, Gr, Gr_start=prev, factor=1.5, log=log,
+                             newton_opts=newton_opts)
                 prev = Gr
             ctx.set_params(Gr)
             Up, _ = base_flow_sensitivity(ctx, base)
             ctx.set_terms(terms)
-            r = krylov_schur(ctx, base, k, m, v0, tol=tol)
+            if chebyshev > 0:
+                r = krylov_schur_chebyshev(ctx, base, k, m, v0, degree=chebyshev, tol=tol,
+                                           max_restarts=max_restarts)
+            else:
+                r = krylov_schur(ctx, base, k, m, v0, tol=tol, max_restarts=max_restarts)
             lead = 0
             lam, x = r.lam[lead], r.X[lead]
             if lam.imag < 0 and len(r.lam) > 1 and abs(r.lam[1] - np.conj(lam)) < 1e-8 * abs(lam):
                 lam, x = r.lam[1], r.X[1]
-            _, ys = left_eigvecs(ctx, base, [lam], k, m, seed, tol=tol)
+            _, ys = left_eigvecs(ctx, base, [lam], k, m, seed, tol=tol, max_restarts=max_restarts)
             dl = total_dlam_dGr(ctx, base, x, ys[0], Up)
             hist.append({"Gr": Gr, "lam": lam, "dlam_dGr": dl, "nvec": r.nvec})
             if log:
