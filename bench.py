@@ -30,10 +30,12 @@ Usage: python bench.py [--steps K] [--warmup W] [--n N] [--nvec M]
        python bench.py --ingest-pmc FETCH WRITE CFETCH CWRITE
            reads four rocprofv3 --pmc output folders (FETCH_SIZE and
            WRITE_SIZE of a bench run, then of the copy calibration) and
-           writes profiles/traffic.json: HBM bytes per launch of the
-           dominant kernel, scaled so the copy reads and writes exactly its
-           size, tagged with a hash of the kernel source (a later edit of
-           the source makes the entry stale and bench.py reports null).
+           writes profiles/traffic.json: HBM bytes per launch of each
+           kernel of the Krylov vector (stencil, divergence-forming and
+           plain transforms, correction), scaled so the copy reads and
+           writes exactly its size, each tagged with a hash of its source
+           file (a later edit of the source makes the entry stale and
+           bench.py reports null for it).
 """
 import csv
 import glob
@@ -52,12 +54,11 @@ METRIC = ("Krylov vectors/s at 100^3 & 256^3 (FP64 vs mixed+adjoint) at stated "
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 COPY_BYTES = 1 << 31         # copy calibration: 2 GiB read + 2 GiB written
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
-# the dominant kernel of the timed step (the TPF axis transform) and its source
-DOMINANT_SRC = os.path.join(ROOT, "paper_1905_11601_amd", "csrc", "kernels_tpf.hip")
+CSRC = os.path.join(ROOT, "paper_1905_11601_amd", "csrc")
 
 
 def transform_kernel(n):
-    """Name of the axis-transform kernel the library runs for n cells (the
+    """Name of the per-axis transform kernel the library runs for n cells (the
     register-resident variant for 193..256 cells, else the streaming one)."""
     ne = n - n // 2
     return "k_axis_res" if 96 < ne <= 128 else "k_axis_sym"
@@ -68,6 +69,43 @@ def transform_work(n):
     two half-size products per pencil, each input and output value moved once."""
     ne, no = n - n // 2, n // 2
     return 2.0 * (ne * ne + no * no) * n * n, 16.0 * n ** 3
+
+
+def stage_kernels(n, planes=False):
+    """stage -> (kernels, source file, algorithmic bytes per launch, flops per
+    launch) of one FP64 Krylov vector at n^3 (planes: the opt-in plane
+    kernels of the TPF solve, else the per-axis ones)."""
+    npts, ncell = (n + 2) ** 3, n ** 3
+    f1, _ = transform_work(n)
+    out = {"jacvec": (("k_jac_tiled",), "kernels_stencil.hip", stencil_bytes_per_point() * npts,
+                      0.0),
+           "correct": (("k_correct<",), "kernels_stencil.hip",
+                       (3 + 3 + 1) * 8 * ncell + 3 * 8 * npts, 0.0)}
+    if planes:
+        # divergence from the faces (3 reads) + x and y forward transforms,
+        # one write; then z forward / scale / z inverse and y / x inverse,
+        # each one read and one write and two transforms
+        out["div"] = (("k_plane_fwd",), "kernels_tpf_plane.hip", 32.0 * ncell, 2 * f1)
+        out["transform"] = (("k_plane_mid", "k_plane_inv"), "kernels_tpf_plane.hip",
+                            16.0 * ncell, 2 * f1)
+    else:
+        out["div"] = (("k_axis_sym:div",), "kernels_tpf.hip", 32.0 * ncell, f1)
+        out["transform"] = ((transform_kernel(n),), "kernels_tpf.hip", 16.0 * ncell, f1)
+    return out
+
+
+def roof_of(work_bytes, flops, seconds):
+    """Roofline entry of one launch: bound by whichever of HBM and FP64 MFMA
+    is tighter for its bytes and flops."""
+    if flops and flops / (FP64_PEAK_TFS * 1e12) > work_bytes / (HBM_PEAK_GBS * 1e9):
+        a = flops / seconds / 1e12
+        return {"bound": "mfma", "achieved": a, "peak": FP64_PEAK_TFS, "unit": "TFLOP/s",
+                "frac": a / FP64_PEAK_TFS}
+    a = work_bytes / seconds / 1e9
+    return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": a / HBM_PEAK_GBS}
+
+
 FP64_PEAK_TFS = 78.6         # MI355X dense FP64 (vector and matrix)
 FP32_PEAK_TFS = 157.3        # MI355X dense FP32 matrix
 
@@ -127,54 +165,72 @@ def _forms_divergence(kernel_name):
     return len(args) == 9 and args[-1].strip() != "0"
 
 
-def _pmc_rows(folder, counter, name_part):
-    """Per-dispatch values (bytes) of `counter` for the plain transforms whose
-    name contains name_part, from a rocprofv3 --pmc csv folder (values in KiB)."""
+def _matches(kernel_name, part):
+    """Kernel selector of stage_kernels: a name part; "k_axis_sym:div" is the
+    divergence-forming instance of k_axis_sym, a plain k_axis_sym part
+    excludes those instances."""
+    if part == "k_axis_sym:div":
+        return _forms_divergence(kernel_name)
+    return part in kernel_name and not _forms_divergence(kernel_name)
+
+
+def _pmc_rows(folder, counter, part):
+    """Per-dispatch values (bytes) of `counter` for the kernels selected by
+    `part` (see _matches), from a rocprofv3 --pmc csv folder (values in KiB)."""
     out = []
     for path in glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True):
         with open(path) as f:
             for row in csv.DictReader(f):
-                if (row["Counter_Name"] == counter and name_part in row["Kernel_Name"]
-                        and not _forms_divergence(row["Kernel_Name"])):
+                if row["Counter_Name"] == counter and _matches(row["Kernel_Name"], part):
                     out.append(float(row["Counter_Value"]) * 1024.0)
     return out
 
 
 def ingest_pmc(fetch_dir, write_dir, cfetch_dir, cwrite_dir, n):
-    DOMINANT = transform_kernel(n)
-    fetch = _pmc_rows(fetch_dir, "FETCH_SIZE", DOMINANT)
-    write = _pmc_rows(write_dir, "WRITE_SIZE", DOMINANT)
     # the copy is the largest dispatch of the calibration run
     cf = max(_pmc_rows(cfetch_dir, "FETCH_SIZE", ""))
     cw = max(_pmc_rows(cwrite_dir, "WRITE_SIZE", ""))
-    if not fetch or not write:
-        raise SystemExit(f"no {DOMINANT} dispatches in the pmc folders")
     kf, kw = COPY_BYTES / cf, COPY_BYTES / cw
-    f_avg, w_avg = sum(fetch) / len(fetch), sum(write) / len(write)
-    rec = {"kernel": DOMINANT, "grid": n, "source": os.path.relpath(DOMINANT_SRC, ROOT),
-           "source_sha256": source_hash(DOMINANT_SRC),
-           "dispatches": [len(fetch), len(write)],
-           "fetch_bytes_raw": f_avg, "write_bytes_raw": w_avg,
-           "copy_fetch_bytes_raw": cf, "copy_write_bytes_raw": cw,
-           "fetch_scale": kf, "write_scale": kw,
-           "traffic_bytes_per_launch": f_avg * kf + w_avg * kw,
-           "algorithmic_bytes_per_launch": 2 * 8 * n ** 3}
+    rec = {"grid": n, "copy_fetch_bytes_raw": cf, "copy_write_bytes_raw": cw,
+           "fetch_scale": kf, "write_scale": kw, "kernels": {}}
+    for stage, (parts, src, nbytes, _) in stage_kernels(n).items():
+        for part in parts:
+            fetch = _pmc_rows(fetch_dir, "FETCH_SIZE", part)
+            write = _pmc_rows(write_dir, "WRITE_SIZE", part)
+            if not fetch or not write:
+                raise SystemExit(f"no {part} dispatches in the pmc folders")
+            f_avg, w_avg = sum(fetch) / len(fetch), sum(write) / len(write)
+            rec["kernels"][part] = {
+                "stage": stage, "source": os.path.join("paper_1905_11601_amd", "csrc", src),
+                "source_sha256": source_hash(os.path.join(CSRC, src)),
+                "dispatches": [len(fetch), len(write)],
+                "fetch_bytes_raw": f_avg, "write_bytes_raw": w_avg,
+                "read_bytes_per_launch": f_avg * kf, "write_bytes_per_launch": w_avg * kw,
+                "traffic_bytes_per_launch": f_avg * kf + w_avg * kw,
+                "algorithmic_bytes_per_launch": nbytes}
     with open(TRAFFIC_JSON, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec, indent=1))
 
 
-def traffic_entry(n):
-    """Measured HBM bytes per launch of the dominant kernel, or None when no
-    measurement matches this grid and the current kernel source."""
+def traffic_entry(n, stage, planes=False):
+    """Measured HBM bytes per launch of the kernels of `stage` (their mean),
+    or None when no measurement matches this grid and the current sources."""
     try:
         with open(TRAFFIC_JSON) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("grid") != n or rec.get("source_sha256") != source_hash(DOMINANT_SRC):
+    parts, src, _, _ = stage_kernels(n, planes)[stage]
+    if rec.get("grid") != n:
         return None
-    return rec["traffic_bytes_per_launch"]
+    vals = []
+    for part in parts:
+        k = rec.get("kernels", {}).get(part)
+        if not k or k.get("source_sha256") != source_hash(os.path.join(CSRC, src)):
+            return None
+        vals.append(k["traffic_bytes_per_launch"])
+    return sum(vals) / len(vals)
 
 
 def host_info():
@@ -252,6 +308,8 @@ def main():
     ap.add_argument("--streams", type=int, default=0, choices=(0, 1, 2),
                     help="1: both wall variants on one stream; 2: one stream each; "
                          "0 (default): 2 up to 160^3 cells, else 1")
+    ap.add_argument("--tpf", choices=("auto", "axes", "planes"), default="auto",
+                    help="kernels of the TPF solve (fvk_set_tpf_path)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="oracle baseline: time budget of the all-threads sample")
@@ -289,6 +347,9 @@ def main():
         streams = [torch.cuda.current_stream()] * 2
     runs = [make_inputs(fvk, torch, n, nvec, bc, fvk.FP64, st)
             for bc, st in zip((fvk.CC, fvk.AA), streams)]
+    if args.tpf != "auto":
+        for ctx, _, _ in runs:
+            ctx.set_tpf_path(fvk.TPF_AXES if args.tpf == "axes" else fvk.TPF_PLANES)
     Ys = []
     for (_, _, X), st in zip(runs, streams):
         with torch.cuda.stream(st):
@@ -346,31 +407,17 @@ def main():
     ncell = n ** 3
     per = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in stages.items()}
     dominant = max(("jacvec", "transform", "correct", "div"), key=lambda k: stages[k][0])
-    if dominant == "transform":
-        # bound by whichever roofline is tighter for this size: at 100 cells
-        # the transform is under the FP64 ridge (6 flop/B) and HBM-bound
-        flops, nbytes = transform_work(n)
-        t_launch = per["transform"] * 1e-3
-        kname = transform_kernel(n) + " (even/odd TPF axis transform, FP64 MFMA)"
-        if flops / (FP64_PEAK_TFS * 1e12) > nbytes / (HBM_PEAK_GBS * 1e9):
-            achieved = flops / t_launch / 1e12
-            roof = {"kernel": kname, "bound": "mfma", "achieved": achieved,
-                    "peak": FP64_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFS}
-        else:
-            achieved = nbytes / t_launch / 1e9
-            roof = {"kernel": kname, "bound": "hbm", "achieved": achieved,
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
-        roof.update({"traffic": traffic_entry(n), "traffic_unit": "bytes per launch",
-                     "algorithmic_bytes_per_launch": nbytes, "flops_per_launch": flops,
-                     "per_launch_us": per["transform"] * 1e3})
-    else:
-        bytes_per = {"jacvec": stencil_bytes_per_point() * npts,
-                     "correct": (3 + 3 + 1) * 8 * ncell + 3 * 8 * npts,
-                     "div": (3 * 8 + 8) * ncell}[dominant]
-        achieved = bytes_per / (per[dominant] * 1e-3) / 1e9
-        roof = {"kernel": dominant, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "per_launch_us": per[dominant] * 1e3}
+    kernels = stage_kernels(n, planes=args.tpf == "planes")
+    parts, src, nbytes, flops = kernels[dominant]
+    roof = {"kernel": " + ".join(p.split(":")[0] for p in parts) + f" ({dominant} stage)"}
+    roof.update(roof_of(nbytes, flops, per[dominant] * 1e-3))
+    roof.update({"traffic": traffic_entry(n, dominant, args.tpf == "planes"),
+                 "traffic_unit": "bytes per launch",
+                 "algorithmic_bytes_per_launch": nbytes, "flops_per_launch": flops,
+                 "per_launch_us": per[dominant] * 1e3, "source": src})
+    roof["stages"] = {k: dict(roof_of(kernels[k][2], kernels[k][3], per[k] * 1e-3),
+                              us=per[k] * 1e3, kernels=list(kernels[k][0]))
+                      for k in kernels if stages.get(k, (0, 0))[1]}
     roof["stages_us_per_launch"] = {k: v * 1e3 for k, v in per.items() if stages[k][1]}
 
     out = {

@@ -123,6 +123,26 @@ fvk_status fvk_set_terms(fvk_ctx *ctx, int mask);
 fvk_status fvk_set_shift(fvk_ctx *ctx, double sigma);
 fvk_status fvk_get_shift(const fvk_ctx *ctx, double *sigma);
 fvk_status fvk_set_precision(fvk_ctx *ctx, int prec);
+/* Kernels of the TPF Poisson solve of the SIMPLE pass (Sec. 3.1, eqs
+ * (16)-(18)); the result is the same up to rounding order.
+ *   FVK_TPF_AUTO   (default) FVK_TPF_AXES;
+ *   FVK_TPF_AXES   six launches, one per axis transform (and direction);
+ *   FVK_TPF_PLANES three launches whose blocks hold one plane of the cell
+ *                  array in LDS: the x and y forward transforms (with the
+ *                  divergence formed from the faces) per z plane; the z
+ *                  forward transform, the scaling and the z inverse per y
+ *                  plane; the y and x inverse transforms per z plane.  Only
+ *                  for 4 <= nx, ny, nz <= 128.  Measured slower than the
+ *                  per-axis kernels at every size from 48^3 to 128^3 (one
+ *                  block per plane keeps at most 128 of the 256 compute
+ *                  units busy through a chain of dependent steps), so it is
+ *                  never chosen automatically.
+ * Returns FVK_EINVAL for an unknown value or FVK_TPF_PLANES on a grid it
+ * does not fit.  fvk_get_tpf_path reports the kernels the solve runs
+ * (FVK_TPF_AXES or FVK_TPF_PLANES). */
+typedef enum { FVK_TPF_AUTO = 0, FVK_TPF_AXES = 1, FVK_TPF_PLANES = 2 } fvk_tpf_path;
+fvk_status fvk_set_tpf_path(fvk_ctx *ctx, int path);
+fvk_status fvk_get_tpf_path(const fvk_ctx *ctx, int *path);
 /* SIMPLE loop control (Sec. 3.1): stop when max |D v| < tol (default 1e-9,
  * the paper's pointwise criterion), at most max_passes passes (default 10). */
 fvk_status fvk_set_simple(fvk_ctx *ctx, double tol, int max_passes);

@@ -18,6 +18,7 @@ import numpy as np
 CC, AA = 0, 1
 UNIFORM, SINE, TANH = 0, 1, 2
 FP64, MIXED = 0, 1
+TPF_AUTO, TPF_AXES, TPF_PLANES = 0, 1, 2
 # coupling terms of the linearised operator (fvk_set_terms bit masks)
 TERM_BUOYANCY, TERM_U_GRAD_V, TERM_V_GRAD_U = 1, 2, 4
 TERM_U_GRAD_T = (8, 16, 32)        # U dT/dx, V dT/dy, W dT/dz
@@ -119,6 +120,18 @@ class Ctx:
     def set_precision(self, prec):
         self._check(self.lib.fvk_set_precision(self.h, prec))
         self.prec = prec
+
+    def set_tpf_path(self, path):
+        """Kernels of the TPF solve (fvk_set_tpf_path): TPF_AUTO (= TPF_AXES),
+        TPF_AXES (one launch per axis transform) or TPF_PLANES (three plane
+        launches, axes of 4 .. 128 cells; measured slower, opt-in)."""
+        self._check(self.lib.fvk_set_tpf_path(self.h, int(path)))
+
+    def tpf_path(self):
+        """TPF_AXES or TPF_PLANES: the kernels the solve runs."""
+        v = ctypes.c_int()
+        self._check(self.lib.fvk_get_tpf_path(self.h, ctypes.byref(v)))
+        return v.value
 
     def set_simple(self, tol, max_passes):
         self._check(self.lib.fvk_set_simple(self.h, float(tol), int(max_passes)))

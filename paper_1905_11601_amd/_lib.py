@@ -42,6 +42,8 @@ SIGNATURES = {
     "fvk_set_shift": (c_int, [c_void_p, c_double]),
     "fvk_get_shift": (c_int, [c_void_p, P(c_double)]),
     "fvk_set_precision": (c_int, [c_void_p, c_int]),
+    "fvk_set_tpf_path": (c_int, [c_void_p, c_int]),
+    "fvk_get_tpf_path": (c_int, [c_void_p, P(c_int)]),
     "fvk_set_simple": (c_int, [c_void_p, c_double, c_int]),
     "fvk_layout": (c_int, [c_void_p, P(c_size_t), P(c_size_t), P(c_size_t)]),
     "fvk_grid_axis": (c_int, [c_void_p, c_int, P(c_double), P(c_double), P(c_double)]),

@@ -81,5 +81,8 @@ def left_eigvecs(ctx, base, lam, k, m, seed_vec, tol=1e-10, max_restarts=200):
     out = []
     for l in np.atleast_1d(lam):
         q = int(np.argmin(np.abs(r.lam - np.conj(l))))
+        if abs(r.lam[q] - np.conj(l)) > 1e-6 * max(1.0, abs(l)):
+            raise RuntimeError(f"no left eigenvalue matches {l}: the transposed solve found "
+                               f"{r.lam} (raise k)")
         out.append(r.X[q])
     return r, out

@@ -10,7 +10,7 @@ OUT = os.path.join(HERE, "libfvk.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["capi.cpp", "solvers.cpp", "eig.cpp", "kernels_stencil.hip", "kernels_tpf.hip",
-           "kernels_blas.hip", "kernels_psi.hip", "noalloc.hip"]
+           "kernels_blas.hip", "kernels_psi.hip", "kernels_tpf_plane.hip", "noalloc.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-Wall",
          "-Wno-unused-result",

@@ -31,8 +31,11 @@ def main(argv=None):
     ap.add_argument("--gr0", type=float, default=3.4e6, help="starting Grashof number")
     ap.add_argument("--coarse", type=int, default=0,
                     help="start the steady state from this coarser grid (0: continuation here)")
-    ap.add_argument("--newton-tol", type=float, default=1e-9)
-    ap.add_argument("--k", type=int, default=4)
+    ap.add_argument("--newton-tol", type=float, default=1e-8,
+                    help="steady-state residual tolerance (the FP64 floor of max |P F| on "
+                         "strongly stretched grids is ~1e-9)")
+    ap.add_argument("--k", type=int, default=8,
+                    help="eigenvalues per solve (every pair near the crossing must fit)")
     ap.add_argument("--m", type=int, default=60)
     ap.add_argument("--tol", type=float, default=1e-9, help="Ritz residual tolerance")
     ap.add_argument("--gr-rtol", type=float, default=1e-6)
@@ -85,6 +88,8 @@ def main(argv=None):
            "f_critical": abs(lam.imag) / (2 * math.pi),
            "history": [{"Gr": h["Gr"], "lam": [complex(h["lam"]).real, complex(h["lam"]).imag],
                         "dlam_dGr": [complex(h["dlam_dGr"]).real, complex(h["dlam_dGr"]).imag],
+                        "slope": h["slope"], "step_from": h["step_from"],
+                        "eigenvalues": [[v.real, v.imag] for v in h["eigenvalues"]],
                         "nvec": h["nvec"]} for h in hist if "lam" in h],
            "psi_extrema_at_Gr0": psi, "base_seconds": t_base, "critical_seconds": t_crit}
     print(json.dumps(out))

@@ -538,6 +538,22 @@ fvk_status fvk_set_precision(fvk_ctx *ctx, int prec) {
     return FVK_OK;
 }
 
+fvk_status fvk_set_tpf_path(fvk_ctx *ctx, int path) {
+    if (!ctx) return FVK_EINVAL;
+    if (path != FVK_TPF_AUTO && path != FVK_TPF_AXES && path != FVK_TPF_PLANES)
+        return fail(ctx, FVK_EINVAL, "bad TPF path");
+    if (path == FVK_TPF_PLANES && !tpf_plane_fits(ctx->n))
+        return fail(ctx, FVK_EINVAL, "TPF plane kernels need 4 .. 128 cells per axis");
+    ctx->tpf_path = path;
+    return FVK_OK;
+}
+
+fvk_status fvk_get_tpf_path(const fvk_ctx *ctx, int *path) {
+    if (!ctx || !path) return FVK_EINVAL;
+    *path = tpf_uses_planes(ctx) ? FVK_TPF_PLANES : FVK_TPF_AXES;
+    return FVK_OK;
+}
+
 fvk_status fvk_mixed_passes(const fvk_ctx *ctx, int *passes, int *calibrated) {
     if (!ctx) return FVK_EINVAL;
     if (passes) *passes = ctx->mixed_passes;

@@ -124,6 +124,7 @@ struct fvk_ctx {
     int mixed_passes = 2;           // fixed pass count of asynchronous mixed calls
     bool mixed_calibrated = false;  // mixed_passes set by an adaptive forward call
     double shift = 0.0;             // fvk_set_shift: Krylov operator A + shift P
+    int tpf_path = 0;               // fvk_set_tpf_path (FVK_TPF_*)
     fvk::AxisHost ax[3];
     fvk::Eig1D eig[3];
     fvk::EigSym esym[3];
@@ -186,6 +187,11 @@ bool noalloc_prepare(std::string *err);
 void tpf_solve(fvk_ctx *ctx, const double *b, double *phi, bool fp32, hipStream_t st,
                const double *vel = nullptr, int win = 0);
 bool tpf_fuses_div(const fvk_ctx *ctx);
+// the fused plane kernels (kernels_tpf_plane.hip): every axis 4 .. 128 cells
+bool tpf_plane_fits(const int n[3]);
+bool tpf_uses_planes(const fvk_ctx *ctx);
+void tpf_solve_planes(fvk_ctx *ctx, const double *b, double *phi, bool fp32, hipStream_t st,
+                      const double *vel, int win);
 // phi = L_bc^+ b in every plane normal to axis `normal` (b, c the other two
 // axes), FP64; the constant mode of each plane gets coefficient 0
 void tpf_solve_plane(fvk_ctx *ctx, const double *b, double *phi, int normal, hipStream_t st);

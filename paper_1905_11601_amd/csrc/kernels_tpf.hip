@@ -11,46 +11,17 @@
 #include <algorithm>
 
 #include "fvk_internal.h"
+#include "tpf_common.h"
 
 namespace fvk {
 
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-template <typename T>
-struct Mfma;
-// Operands (both types): lane l holds A[l % 16][l / 16] and B[l / 16][l % 16].
-// Result row of accumulator register r in lane l (column l % 16) differs:
-// f64 places row 4 r + l / 16, f32 places row 4 (l / 16) + r (checked by an
-// in-bounds probe on gfx950).
-template <>
-struct Mfma<double> {
-    typedef d4 acc;
-    static __device__ __forceinline__ acc op(double a, double b, acc c) {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int lane, int r) { return 4 * r + (lane >> 4); }
-};
-template <>
-struct Mfma<float> {
-    typedef f4 acc;
-    static __device__ __forceinline__ acc op(float a, float b, acc c) {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row(int lane, int r) { return 4 * (lane >> 4) + r; }
-};
+using tpf::Mfma;
+using tpf::lds_barrier;
+using tpf::recip;
 
 constexpr int TM = 32, TN = 64, KC = 16, NT = 256;
-
-// LDS-only workgroup barrier: orders LDS traffic without waiting for global
-// loads or stores in flight.
-__device__ __forceinline__ void lds_barrier() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-    __builtin_amdgcn_s_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
 
 struct AxisView {
     int na;      // transform length (rows of M, K of the product)
@@ -179,15 +150,6 @@ struct SymTile {
     static constexpr int NX = (TP * KC + NTT - 1) / NTT;
 };
 
-// 1 / d to full double precision: hardware estimate + two Newton steps
-__device__ __forceinline__ double recip(double d) {
-    double r = __builtin_amdgcn_rcp(d);
-    r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
-    r = __builtin_fma(__builtin_fma(-d, r, 1.0), r, r);
-    return r;
-}
-__device__ __forceinline__ float recip(float d) { return 1.0f / d; }
-
 // The even/odd transform kernel (see SymTile).  DIV (x-axis forward only):
 // the input is not an array of cell values but the velocity fields X (3
 // stored fields, geometry dg); the value at cell
@@ -225,28 +187,11 @@ __global__ __launch_bounds__(64 * NW) void k_axis_sym(const Tc *__restrict__ M, 
     // cell (i, j, k) of pencil column gp (x axis: columns = (k, j)) at x index kc
     auto face_loads = [&](int gp, int kc, double *f) {
         const int kz = col_hi(v, gp), jy = gp - kz * v.n0;
-        const int i = kc + 1, j = jy + 1, k = kz + 1;
-        const long p = (long(k) * dg.np[1] + j) * dg.np[0] + i;
-        f[0] = X[p];
-        f[1] = X[p - 1];
-        f[2] = X[dg.F + p];
-        f[3] = X[dg.F + p - dg.s[1]];
-        f[4] = X[2 * dg.F + p];
-        f[5] = X[2 * dg.F + p - dg.s[2]];
+        tpf::cell_faces(dg, X, kc + 1, jy + 1, kz + 1, f);
     };
     auto face_div = [&](int gp, int kc, const double *f) -> double {
         const int kz = col_hi(v, gp), jy = gp - kz * v.n0;
-        const int i = kc + 1, j = jy + 1, k = kz + 1;
-        const double hx = dg.ax[0].ih[i], hy = dg.ax[1].ih[j], hz = dg.ax[2].ih[k];
-        if (DIV == 1) return (f[0] - f[1]) * hx + (f[2] - f[3]) * hy + (f[4] - f[5]) * hz;
-        // D W^-1 v: interior faces scaled by 1/W, wall faces 0
-        const double up = i < dg.n[0] ? f[0] * (dg.ax[0].id[i] * hy * hz) : 0.0;
-        const double um = i > 1 ? f[1] * (dg.ax[0].id[i - 1] * hy * hz) : 0.0;
-        const double vp = j < dg.n[1] ? f[2] * (dg.ax[1].id[j] * hz * hx) : 0.0;
-        const double vm = j > 1 ? f[3] * (dg.ax[1].id[j - 1] * hz * hx) : 0.0;
-        const double wp = k < dg.n[2] ? f[4] * (dg.ax[2].id[k] * hx * hy) : 0.0;
-        const double wm = k > 1 ? f[5] * (dg.ax[2].id[k - 1] * hx * hy) : 0.0;
-        return (up - um) * hx + (vp - vm) * hy + (wp - wm) * hz;
+        return tpf::cell_div<DIV ? DIV : 1>(dg, f, kc + 1, jy + 1, kz + 1);
     };
     auto fetch = [&](int c) {
         const int kb = c * KC;
@@ -783,8 +728,16 @@ bool tpf_fuses_div(const fvk_ctx *ctx) {
     return ctx->n[0] <= kSymMax && ne <= 128;
 }
 
+bool tpf_uses_planes(const fvk_ctx *ctx) {
+    return ctx->tpf_path == FVK_TPF_PLANES && tpf_plane_fits(ctx->n);
+}
+
 void tpf_solve(fvk_ctx *ctx, const double *b, double *phi, bool fp32, hipStream_t st,
                const double *vel, int win) {
+    if (tpf_uses_planes(ctx)) {
+        tpf_solve_planes(ctx, b, phi, fp32, st, vel, win);
+        return;
+    }
     const Workspace &w = ctx->ws;
     if (fp32) {
         AxisFactors<float> F[3];

@@ -176,13 +176,22 @@ def total_dlam_dGr(ctx, base, x, y, Up):
     return _cdot(ctx, y.reshape(-1), dAx) / _cdot(ctx, y.reshape(-1), x.reshape(-1))
 
 
-def critical_gr(ctx, base, Gr0, v0, seed, k=4, m=40, tol=1e-10, gr_rtol=1e-7, max_it=12,
+def critical_gr(ctx, base, Gr0, v0, seed, k=8, m=60, tol=1e-10, gr_rtol=1e-7, max_it=12,
                 log=None, terms=None, chebyshev=0, max_restarts=400, newton_opts=None):
     """Newton iteration on Gr for Re lambda_lead(Gr) = 0 (the paper's critical
     Grashof number).  ``base`` (in/out) must be a steady state at Gr0.  Each
     iteration: Newton steady state at the current Gr (from the previous one),
-    the leading right and left eigenpairs (Krylov-Schur on A and A^T), U', and
-    Gr <- Gr - Re lambda / Re(d lambda / d Gr).  Returns a history list.
+    the k rightmost eigenvalues (Krylov-Schur on A), the leading one (largest
+    real part, Im >= 0 of a pair) with its left eigenvector (Krylov-Schur on
+    A^T), U', and Gr <- Gr - Re lambda / Re(d lambda / d Gr).  Returns a
+    history list (each entry also lists the k eigenvalues found).
+
+    k must hold every pair near the crossing: with fewer, the solve can
+    return a set that misses the rightmost one.  When two successive
+    iterates lead with the same mode, the secant slope of Re lambda checks
+    the adjoint derivative; if they differ in sign or by more than a factor
+    of 3, the step uses the secant (the adjoint estimate divides by y^H x,
+    which is small for the strongly non-normal operators near the onset).
 
     terms: coupling terms kept in the eigenvalue problem (fvk TERM_* mask, the
     mechanism experiment of Sec. 4.2); the steady states and U' always use
@@ -200,6 +209,7 @@ def critical_gr(ctx, base, Gr0, v0, seed, k=4, m=40, tol=1e-10, gr_rtol=1e-7, ma
     hist = []
     Gr = Gr0
     prev = Gr0
+    last = None          # (Gr, lambda) of the previous iterate
     try:
         for it in range(max_it):
             ctx.set_terms(full)
@@ -216,16 +226,28 @@ def critical_gr(ctx, base, Gr0, v0, seed, k=4, m=40, tol=1e-10, gr_rtol=1e-7, ma
                                            max_restarts=max_restarts)
             else:
                 r = krylov_schur(ctx, base, k, m, v0, tol=tol, max_restarts=max_restarts)
-            lead = 0
+            # the leading eigenvalue: largest real part, the Im >= 0 member of a pair
+            order = sorted(range(len(r.lam)), key=lambda q: (-round(r.lam[q].real, 12),
+                                                             -r.lam[q].imag))
+            lead = order[0]
             lam, x = r.lam[lead], r.X[lead]
-            if lam.imag < 0 and len(r.lam) > 1 and abs(r.lam[1] - np.conj(lam)) < 1e-8 * abs(lam):
-                lam, x = r.lam[1], r.X[1]
             _, ys = left_eigvecs(ctx, base, [lam], k, m, seed, tol=tol, max_restarts=max_restarts)
             dl = total_dlam_dGr(ctx, base, x, ys[0], Up)
-            hist.append({"Gr": Gr, "lam": lam, "dlam_dGr": dl, "nvec": r.nvec})
+            slope, how = dl.real, "adjoint"
+            if last is not None and abs(lam - last[1]) < 0.02 * abs(lam) and Gr != last[0]:
+                sec = (lam.real - last[1].real) / (Gr - last[0])
+                if sec * slope <= 0 or not (1 / 3 < slope / sec < 3):
+                    slope, how = sec, "secant"
+            hist.append({"Gr": Gr, "lam": lam, "dlam_dGr": dl, "slope": slope, "step_from": how,
+                         "nvec": r.nvec, "eigenvalues": [complex(v) for v in r.lam]})
             if log:
-                log(f"critical Gr it {it}: Gr {Gr:.8g} lambda {lam:.6g} dlam/dGr {dl:.4g}")
-            step = -lam.real / dl.real
+                log(f"critical Gr it {it}: Gr {Gr:.8g} lambda {lam:.6g} dlam/dGr {dl:.4g} "
+                    f"({how} slope {slope:.4g}); found {np.round(r.lam, 5)}")
+            last = (Gr, lam)
+            # the Newton step on Gr, kept within a factor of 2 of the current
+            # Gr (far from the crossing the linear model can point below 0)
+            step = -lam.real / slope
+            step = min(max(step, -0.5 * Gr), Gr)
             Gr = Gr + step
             if abs(step) < gr_rtol * abs(Gr):
                 hist.append({"Gr": Gr, "converged": True})

@@ -130,9 +130,12 @@ VARIANT_CASES = [
 def test_transform_variants(fvk, n, prec):
     """Projection and Krylov vector (forward and transposed) on the boxes
     that select every transform kernel a legal grid size can reach."""
+    import paper_1905_11601_amd as fvk_mod
     print(f"case transform variant n={n} prec={prec}", flush=True)
     bc = 1 if n[1] > 100 else 0
     g, orc, ctx = setup(n, TANH, 1.5, bc, prec=prec)
+    ctx.set_tpf_path(fvk_mod.TPF_AXES)   # the per-axis kernels even where planes fit
+    assert ctx.tpf_path() == fvk_mod.TPF_AXES
     U = base(g, bc)
     x = krylov_input(g, orc, 2001, project=False)
     assert rel_err(ctx.project(dev(x)), orc.project(x)) < TOL
@@ -151,6 +154,65 @@ def test_transform_variants(fvk, n, prec):
     assert rel_err(y, orc.krylov_vec(U, xs)) < TOL
     yT = ctx.simple_krylov_vec(dev(U), dev(xs), transpose=True)
     assert rel_err(yT, orc.krylov_vec_T(U, xs)) < tolT
+
+
+# Boxes for the opt-in plane kernels of the TPF solve (every axis 4 .. 128
+# cells): the smallest box; odd and even extents (middle values of the
+# even/odd fold); 65..96 cells (three row tiles per half, two of the eight
+# waves idle); 128 cells on each axis in turn (largest LDS plane, four row
+# tiles); a cube.
+PLANE_CASES = [
+    ((4, 4, 4), 0), ((17, 33, 9), 0), ((24, 20, 28), 0), ((70, 66, 9), 0), ((128, 6, 5), 0),
+    ((5, 128, 6), 0), ((6, 5, 128), 0), ((48, 48, 48), 0),
+    ((17, 33, 9), 1), ((24, 20, 28), 1), ((70, 9, 66), 1), ((128, 5, 128), 1),
+]
+
+
+@pytest.mark.parametrize("n,prec", PLANE_CASES,
+                         ids=[f"{'x'.join(map(str, c[0]))}-{'mixed' if c[1] else 'fp64'}"
+                              for c in PLANE_CASES])
+def test_tpf_plane_kernels(fvk, n, prec):
+    """Projection (forward and transposed) and Krylov vectors with the plane
+    kernels of the TPF solve against the oracle, and against the per-axis
+    kernels on the same inputs."""
+    import paper_1905_11601_amd as fvk_mod
+    print(f"case tpf planes n={n} prec={prec}", flush=True)
+    bc = 1 if n[0] % 2 else 0
+    g, orc, ctx = setup(n, TANH, 1.5, bc, prec=prec)
+    assert ctx.tpf_path() == fvk_mod.TPF_AXES     # the default
+    ctx.set_tpf_path(fvk_mod.TPF_PLANES)
+    assert ctx.tpf_path() == fvk_mod.TPF_PLANES
+    U = base(g, bc)
+    x = krylov_input(g, orc, 2001, project=False)
+    tolT = TOL if prec == 0 else 1e-9
+    Px = ctx.project(dev(x))
+    PTx = ctx.project(dev(x), transpose=True)
+    assert rel_err(Px, orc.project(x)) < TOL
+    assert rel_err(PTx, orc.project_T(x)) < tolT
+    xs = krylov_input(g, orc, 2000)
+    y, passes, dmax = ctx.simple_krylov_vec(dev(U), dev(xs), info=True)
+    assert dmax < 1e-9 and (passes == 1 if prec == 0 else passes >= 2)
+    assert rel_err(y, orc.krylov_vec(U, xs)) < TOL
+    yT = ctx.simple_krylov_vec(dev(U), dev(xs), transpose=True)
+    assert rel_err(yT, orc.krylov_vec_T(U, xs)) < tolT
+    ctx.set_tpf_path(fvk_mod.TPF_AXES)
+    assert ctx.tpf_path() == fvk_mod.TPF_AXES
+    assert rel_err(ctx.project(dev(x)), Px.cpu()) < TOL
+    assert rel_err(ctx.simple_krylov_vec(dev(U), dev(xs)), y.cpu()) < TOL
+    ctx.set_tpf_path(fvk_mod.TPF_PLANES)
+    assert rel_err(ctx.simple_krylov_vec(dev(U), dev(xs)), y.cpu()) < TOL
+
+
+def test_tpf_path_rejects_planes_that_do_not_fit(fvk):
+    import paper_1905_11601_amd as fvk_mod
+    ctx = fvk_mod.Ctx(130, 6, 5, grid=fvk_mod.TANH, s=1.5)
+    assert ctx.tpf_path() == fvk_mod.TPF_AXES
+    with pytest.raises(RuntimeError):
+        ctx.set_tpf_path(fvk_mod.TPF_PLANES)
+    with pytest.raises(RuntimeError):
+        ctx.set_tpf_path(7)
+    ctx.set_tpf_path(fvk_mod.TPF_AUTO)
+    assert ctx.tpf_path() == fvk_mod.TPF_AXES
 
 
 def test_asynchronous_calls_record_divergence(fvk):
