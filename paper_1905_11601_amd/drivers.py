@@ -176,6 +176,28 @@ def total_dlam_dGr(ctx, base, x, y, Up):
     return _cdot(ctx, y.reshape(-1), dAx) / _cdot(ctx, y.reshape(-1), x.reshape(-1))
 
 
+def leading_index(lams):
+    """Index of the leading eigenvalue: the largest real part, and of a
+    complex-conjugate pair the member with Im >= 0."""
+    lams = np.asarray(lams)
+    return int(sorted(range(len(lams)), key=lambda q: (-round(lams[q].real, 12),
+                                                        -lams[q].imag))[0])
+
+
+def gr_slope(dl, Gr, lam, last):
+    """d Re(lambda) / d Gr for the Newton step on Gr: the adjoint estimate
+    Re(dl), unless the previous iterate ``last`` = (Gr, lambda) led with the
+    same mode (|lambda - lambda_last| < 2% of |lambda|) and the secant slope
+    through it differs in sign or by more than a factor of 3; then the
+    secant.  Returns (slope, "adjoint" | "secant")."""
+    slope = float(np.real(dl))
+    if last is not None and abs(lam - last[1]) < 0.02 * abs(lam) and Gr != last[0]:
+        sec = (lam.real - last[1].real) / (Gr - last[0])
+        if sec * slope <= 0 or not (1 / 3 < slope / sec < 3):
+            return sec, "secant"
+    return slope, "adjoint"
+
+
 def critical_gr(ctx, base, Gr0, v0, seed, k=8, m=60, tol=1e-10, gr_rtol=1e-7, max_it=12,
                 log=None, terms=None, chebyshev=0, max_restarts=400, newton_opts=None):
     """Newton iteration on Gr for Re lambda_lead(Gr) = 0 (the paper's critical
@@ -226,18 +248,11 @@ def critical_gr(ctx, base, Gr0, v0, seed, k=8, m=60, tol=1e-10, gr_rtol=1e-7, ma
                                            max_restarts=max_restarts)
             else:
                 r = krylov_schur(ctx, base, k, m, v0, tol=tol, max_restarts=max_restarts)
-            # the leading eigenvalue: largest real part, the Im >= 0 member of a pair
-            order = sorted(range(len(r.lam)), key=lambda q: (-round(r.lam[q].real, 12),
-                                                             -r.lam[q].imag))
-            lead = order[0]
+            lead = leading_index(r.lam)
             lam, x = r.lam[lead], r.X[lead]
             _, ys = left_eigvecs(ctx, base, [lam], k, m, seed, tol=tol, max_restarts=max_restarts)
             dl = total_dlam_dGr(ctx, base, x, ys[0], Up)
-            slope, how = dl.real, "adjoint"
-            if last is not None and abs(lam - last[1]) < 0.02 * abs(lam) and Gr != last[0]:
-                sec = (lam.real - last[1].real) / (Gr - last[0])
-                if sec * slope <= 0 or not (1 / 3 < slope / sec < 3):
-                    slope, how = sec, "secant"
+            slope, how = gr_slope(dl, Gr, lam, last)
             hist.append({"Gr": Gr, "lam": lam, "dlam_dGr": dl, "slope": slope, "step_from": how,
                          "nvec": r.nvec, "eigenvalues": [complex(v) for v in r.lam]})
             if log:
