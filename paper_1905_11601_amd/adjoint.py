@@ -78,10 +78,14 @@ def left_eigvecs(ctx, base, lam, k, m, seed_vec, tol=1e-10, max_restarts=200):
     from .eigs import krylov_schur
     v0 = ctx.simple_krylov_vec(base, seed_vec.reshape(ctx.shape4), transpose=True)
     r = krylov_schur(ctx, base, k, m, v0, tol=tol, max_restarts=max_restarts, transpose=True)
+    # the forward and transposed solves reach the same eigenvalue only to
+    # (residual tolerance) x (its condition number 1 / |y^H x|), which is
+    # large for the non-normal operators of these flows: 1e-4 apart at 64^3
+    # with residuals of 1e-9, hence the loose match
     out = []
     for l in np.atleast_1d(lam):
         q = int(np.argmin(np.abs(r.lam - np.conj(l))))
-        if abs(r.lam[q] - np.conj(l)) > 1e-6 * max(1.0, abs(l)):
+        if abs(r.lam[q] - np.conj(l)) > 1e-3 * max(1.0, abs(l)):
             raise RuntimeError(f"no left eigenvalue matches {l}: the transposed solve found "
                                f"{r.lam} (raise k)")
         out.append(r.X[q])

@@ -90,6 +90,10 @@ def main(argv=None):
                         "dlam_dGr": [complex(h["dlam_dGr"]).real, complex(h["dlam_dGr"]).imag],
                         "slope": h["slope"], "step_from": h["step_from"],
                         "eigenvalues": [[v.real, v.imag] for v in h["eigenvalues"]],
+                        "transposed_eigenvalues": [[v.real, v.imag]
+                                                   for v in h["transposed_eigenvalues"]],
+                        "missed_by_forward_solve": [[v.real, v.imag]
+                                                    for v in h["missed_by_forward_solve"]],
                         "nvec": h["nvec"]} for h in hist if "lam" in h],
            "psi_extrema_at_Gr0": psi, "base_seconds": t_base, "critical_seconds": t_crit}
     print(json.dumps(out))

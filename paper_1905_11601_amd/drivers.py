@@ -112,22 +112,42 @@ def prolong_base(ctx_coarse, base_coarse, ctx_fine):
 
 def steady_state_refined(ctx, n_coarse, Gr, log=None, newton_opts=None, coarse_opts=None):
     """Newton steady state at Gr on ctx's grid, started from the steady state
-    of the same problem on a coarser grid (n_coarse cells per axis, reached by
-    continuation in Gr there) interpolated by ``prolong_base``: the fine grid
-    then needs only the last Newton iterations.  Returns (base, report of the
-    fine Newton iteration, coarse stages)."""
+    of the same problem on coarser grids: continuation in Gr on the coarsest
+    (n_coarse: cells per axis, or a list of them from the coarsest up), then
+    on each finer grid the state of the one below interpolated by
+    ``prolong_base`` and a Newton iteration (coarse_opts there, newton_opts on
+    ctx's grid): each grid needs only the last Newton iterations.  Returns
+    (base, report of the fine Newton iteration, coarse stages)."""
     import torch
     from . import Ctx, inputs
-    cctx = Ctx(n_coarse, grid=ctx.grid_kind, s=ctx.s, span_bc=ctx.span_bc, Gr=Gr, Pr=ctx.Pr,
-               device=ctx.device)
+    levels = [int(n_coarse)] if np.isscalar(n_coarse) else [int(v) for v in n_coarse]
+
+    def make(n):
+        return Ctx(n, grid=ctx.grid_kind, s=ctx.s, span_bc=ctx.span_bc, Gr=Gr, Pr=ctx.Pr,
+                   device=ctx.device)
+
+    cctx = make(levels[0])
     _, c, _ = cctx.coords()
     Uc = torch.as_tensor(inputs.conduction_state(c, ctx.span_bc)).cuda()
     stages = steady_state(cctx, Uc, Gr, newton_opts=coarse_opts, log=log)
+    opts = dict(tol=1e-10, gmres_m=100, lin_tol=1e-10, max_newton=10)
+    for n in levels[1:]:
+        mctx = make(n)
+        Um = prolong_base(cctx, Uc, mctx)
+        del Uc
+        cctx.close()
+        mid = dict(opts)
+        mid.update(coarse_opts or {})
+        rep = mctx.newton_step(Um, **mid)
+        stages.append((Gr, rep))
+        if log:
+            log(f"refined Newton on {mctx.n}: status {rep['status']} its {rep['newton_its']} "
+                f"res {rep['res_before']:.2e} -> {rep['res_after']:.2e}")
+        cctx, Uc = mctx, Um
     U = prolong_base(cctx, Uc, ctx)
     del Uc
     cctx.close()
     ctx.set_params(Gr)
-    opts = dict(tol=1e-10, gmres_m=100, lin_tol=1e-10, max_newton=10)
     opts.update(newton_opts or {})
     rep = ctx.newton_step(U, **opts)
     if log:
@@ -250,11 +270,21 @@ def critical_gr(ctx, base, Gr0, v0, seed, k=8, m=60, tol=1e-10, gr_rtol=1e-7, ma
                 r = krylov_schur(ctx, base, k, m, v0, tol=tol, max_restarts=max_restarts)
             lead = leading_index(r.lam)
             lam, x = r.lam[lead], r.X[lead]
-            _, ys = left_eigvecs(ctx, base, [lam], k, m, seed, tol=tol, max_restarts=max_restarts)
+            rT, ys = left_eigvecs(ctx, base, [lam], k, m, seed, tol=tol,
+                                  max_restarts=max_restarts)
             dl = total_dlam_dGr(ctx, base, x, ys[0], Up)
             slope, how = gr_slope(dl, Gr, lam, last)
+            # the transposed solve sees the same spectrum: a pair it finds to
+            # the right of the leading one was missed by the forward solve
+            missed = [complex(np.conj(v)) for v in rT.lam
+                      if v.real > lam.real + 1e-3 * abs(lam) and v.imag <= 0]
             hist.append({"Gr": Gr, "lam": lam, "dlam_dGr": dl, "slope": slope, "step_from": how,
-                         "nvec": r.nvec, "eigenvalues": [complex(v) for v in r.lam]})
+                         "nvec": r.nvec, "eigenvalues": [complex(v) for v in r.lam],
+                         "transposed_eigenvalues": [complex(np.conj(v)) for v in rT.lam],
+                         "missed_by_forward_solve": missed})
+            if missed and log:
+                log(f"critical Gr it {it}: the transposed solve found {np.round(missed, 5)} to "
+                    f"the right of the leading {lam:.5g}")
             if log:
                 log(f"critical Gr it {it}: Gr {Gr:.8g} lambda {lam:.6g} dlam/dGr {dl:.4g} "
                     f"({how} slope {slope:.4g}); found {np.round(r.lam, 5)}")

@@ -55,8 +55,11 @@ def main(argv=None):
     ap.add_argument("--gr", type=float, default=1e6)
     ap.add_argument("--pr", type=float, default=0.71)
     ap.add_argument("--base", choices=("synthetic", "newton", "refined"), default="synthetic")
-    ap.add_argument("--coarse", type=int, default=64, help="coarse grid of --base refined")
+    ap.add_argument("--coarse", default="64",
+                    help="coarse grid(s) of --base refined, coarsest first (e.g. 64,128)")
     ap.add_argument("--newton-tol", type=float, default=1e-9)
+    ap.add_argument("--newton-max", type=int, default=10,
+                    help="Newton iterations on the fine grid of --base refined")
     ap.add_argument("--k", type=int, default=4)
     ap.add_argument("--m", type=int, default=100)
     ap.add_argument("--keep", type=int, default=None)
@@ -102,8 +105,10 @@ def main(argv=None):
                                   log=log)
             fine = None
         else:
-            Ud, fine, stages = steady_state_refined(ctx, args.coarse, args.gr, log=log,
-                                                    newton_opts=dict(tol=args.newton_tol),
+            levels = [int(v) for v in args.coarse.split(",")]
+            Ud, fine, stages = steady_state_refined(ctx, levels, args.gr, log=log,
+                                                    newton_opts=dict(tol=args.newton_tol,
+                                                                     max_newton=args.newton_max),
                                                     coarse_opts=dict(tol=args.newton_tol))
         U = Ud.cpu()
         res_ora = float(orc.residual(U, project=True).abs().max())
@@ -112,7 +117,7 @@ def main(argv=None):
                      "newton_seconds": time.perf_counter() - t0,
                      "oracle_max_projected_residual": res_ora}
         if fine is not None:
-            base_info["coarse_grid"] = args.coarse
+            base_info["coarse_grids"] = levels
             base_info["fine_newton"] = {k: fine[k] for k in ("status", "newton_its",
                                                               "res_before", "res_after",
                                                               "gmres_cycles", "bicgstab_its",
