@@ -79,8 +79,11 @@ def stage_kernels(n, planes=False):
     f1, _ = transform_work(n)
     out = {"jacvec": (("k_jac_tiled",), "kernels_stencil.hip", stencil_bytes_per_point() * npts,
                       0.0),
-           "correct": (("k_correct<",), "kernels_stencil.hip",
-                       (3 + 3 + 1) * 8 * ncell + 3 * 8 * npts, 0.0)}
+           # reads v* (3 fields) and phi on the cells, writes v (3 fields)
+           # on every stored point (walls zeroed); no divergence store on the
+           # last pass of a call
+           "correct": (("k_correct<",), "kernels_stencil.hip", (3 + 1) * 8 * ncell + 3 * 8 * npts,
+                       0.0)}
     if planes:
         # divergence from the faces (3 reads) + x and y forward transforms,
         # one write; then z forward / scale / z inverse and y / x inverse,
@@ -467,7 +470,7 @@ def stage_roofline(per_us, n):
     npts, ncell = (n + 2) ** 3, n ** 3
     out = {}
     for k, nbytes in (("jacvec", stencil_bytes_per_point() * npts),
-                      ("correct", (3 + 3 + 1) * 8 * ncell + 3 * 8 * npts)):
+                      ("correct", (3 + 1) * 8 * ncell + 3 * 8 * npts)):
         if per_us.get(k):
             gbs = nbytes / (per_us[k] * 1e-6) / 1e9
             out[k] = {"us": per_us[k], "GB/s": gbs, "frac_hbm": gbs / HBM_PEAK_GBS}

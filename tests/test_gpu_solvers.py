@@ -379,3 +379,21 @@ def test_critical_grashof_6cube_term_switched(fvk):
     assert abs(hist[-1]["Gr"] - Grc) < 1e-7 * Grc
     assert abs(hist[-2]["lam"]) < 1e-8
     assert ctx.terms == fvk.TERMS_ALL      # restored
+
+
+def test_steady_state_refined_over_two_coarse_grids(fvk):
+    """Coarse-to-fine steady state (continuation on 6^3, Newton on 8^3 and then
+    on 12^3 from the interpolated states) against continuation on 12^3
+    itself: the same converged state (tanh grid, CC walls, Gr 1e5), and the
+    oracle's residual of it below the Newton tolerance."""
+    from paper_1905_11601_amd.drivers import steady_state, steady_state_refined
+    print("case refined steady state 6 -> 8 -> 12", flush=True)
+    g, orc, ctx = setup((12, 12, 12), TANH, 1.5, 0, Gr=1e5)
+    U, rep, stages = steady_state_refined(ctx, [6, 8], 1e5, newton_opts=dict(tol=1e-10),
+                                          coarse_opts=dict(tol=1e-10))
+    assert rep["status"] == 0 and rep["res_after"] < 1e-10
+    assert len(stages) >= 2 and stages[-1][1]["status"] == 0       # the 8^3 Newton
+    Ud = dev(torch.as_tensor(inputs.conduction_state(tuple(a.c for a in g.ax), 0)))
+    steady_state(ctx, Ud, 1e5, newton_opts=dict(tol=1e-10))
+    assert rel_err(U, Ud.cpu()) < 1e-8
+    assert float(orc.residual(U.cpu(), project=True).abs().max()) < 1e-9
