@@ -24,7 +24,9 @@ their per-stage roofline) and `lambda_error` (the rightmost eigenvalues at
 100^3 in FP64 and in mixed precision, and their difference).
 
 Usage: python bench.py [--steps K] [--warmup W] [--n N] [--nvec M]
-       [--streams S] [--no-cpu-baseline] [--no-extra] [--no-eig] [--no-256]
+       [--streams S] [--tpf auto|axes|planes] [--no-cpu-baseline] [--no-extra]
+       [--no-eig] [--no-256]
+       (--tpf planes: the opt-in plane kernels of the TPF solve, for comparison)
        python bench.py --copy-calibration          (a 2 GiB device copy, for
                                                     rocprofv3 --pmc scaling)
        python bench.py --ingest-pmc FETCH WRITE CFETCH CWRITE
