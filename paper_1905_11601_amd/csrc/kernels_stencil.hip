@@ -13,6 +13,7 @@
 #include <type_traits>
 
 #include "fvk_internal.h"
+#include "xcd.h"
 
 namespace fvk {
 
@@ -28,13 +29,6 @@ struct Blk {
     int x, y, z;
     long lin;   // logical linear index (unique per block)
 };
-// Logical index of hardware block b of nb: block b runs on XCD b % 8 as that
-// XCD's (b / 8)-th block; XCDs 0 .. r-1 (r = nb % 8) get q + 1 = nb / 8 + 1
-// consecutive logical indices, the others q -- a bijection for any nb.
-__device__ __forceinline__ long xcd_remap(long b, long nb) {
-    const long q = nb / 8, r = nb % 8, x = b % 8;
-    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + b / 8;
-}
 
 __device__ __forceinline__ Blk xcd_block() {
     const int nbx = gridDim.x, nby = gridDim.y;

@@ -12,6 +12,7 @@
 
 #include "fvk_internal.h"
 #include "tpf_common.h"
+#include "xcd.h"
 
 namespace fvk {
 
@@ -174,7 +175,10 @@ __global__ __launch_bounds__(64 * NW) void k_axis_sym(const Tc *__restrict__ M, 
     typedef typename Mfma<Tc>::acc acc_t;
     const int n = v.na, nh = n / 2, ne = n - nh, no = nh;
     const Tc *Me = M, *Mo = M + long(ne) * ne;
-    const int p0 = blockIdx.x * TP;
+    // XCD-aware tile order: neighbouring pencil tiles share the cache lines a
+    // row of the array straddles (rows of 100 cells are not multiples of 16),
+    // so consecutive tiles go to the same XCD and its L2 serves the second
+    const int p0 = int(xcd_remap(blockIdx.x, gridDim.x)) * TP;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const int nchunk = (ne + KC - 1) / KC;

@@ -397,3 +397,25 @@ def test_steady_state_refined_over_two_coarse_grids(fvk):
     steady_state(ctx, Ud, 1e5, newton_opts=dict(tol=1e-10))
     assert rel_err(U, Ud.cpu()) < 1e-8
     assert float(orc.residual(U.cpu(), project=True).abs().max()) < 1e-9
+
+
+def test_critical_command_line_6cube(fvk, capsys):
+    """The critical-Grashof command line end to end on the 6^3 uniform grid
+    with conducting walls (continuation, Psi extrema, Newton on Gr with 4
+    eigenvalues per solve): the oracle's crossing stored by
+    tests/golden/make_critical6.py."""
+    import json
+    import os
+    from paper_1905_11601_amd import critical
+    print("case critical command line 6^3", flush=True)
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                       "critical_6cube.json")))
+    rc = critical.main(["--n", "6", "--grid", "uniform", "--s", "0", "--bc", "CC",
+                        "--gr0", str(gold["Gr0"]), "--k", "4", "--m", "40", "--tol", "1e-12",
+                        "--gr-rtol", "1e-10", "--newton-tol", "1e-11", "--max-it", "10"])
+    out = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    assert rc == 0 and out["converged"]
+    assert abs(out["Gr_critical"] - gold["Gr_critical"]) < 1e-7 * gold["Gr_critical"]
+    assert abs(2 * np.pi * out["f_critical"] - abs(gold["lambda_critical"][1])) < 1e-6
+    assert set(out["psi_extrema_at_Gr0"]) == {"x", "y", "z"}
+    assert all(h["step_from"] in ("adjoint", "secant") for h in out["history"])
