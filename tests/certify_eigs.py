@@ -60,6 +60,8 @@ def main(argv=None):
     ap.add_argument("--newton-tol", type=float, default=1e-9)
     ap.add_argument("--newton-max", type=int, default=10,
                     help="Newton iterations on the fine grid of --base refined")
+    ap.add_argument("--gmres-m", type=int, default=100,
+                    help="GMRES restart length of the Newton linear solves (<= 400)")
     ap.add_argument("--k", type=int, default=4)
     ap.add_argument("--m", type=int, default=100)
     ap.add_argument("--keep", type=int, default=None)
@@ -101,15 +103,18 @@ def main(argv=None):
         c = tuple(a.c for a in g.ax)
         if args.base == "newton":
             Ud = torch.as_tensor(inputs.conduction_state(c, bc)).cuda()
-            stages = steady_state(ctx, Ud, args.gr, newton_opts=dict(tol=args.newton_tol),
+            stages = steady_state(ctx, Ud, args.gr,
+                                  newton_opts=dict(tol=args.newton_tol, gmres_m=args.gmres_m),
                                   log=log)
             fine = None
         else:
             levels = [int(v) for v in args.coarse.split(",")]
             Ud, fine, stages = steady_state_refined(ctx, levels, args.gr, log=log,
                                                     newton_opts=dict(tol=args.newton_tol,
-                                                                     max_newton=args.newton_max),
-                                                    coarse_opts=dict(tol=args.newton_tol))
+                                                                     max_newton=args.newton_max,
+                                                                     gmres_m=args.gmres_m),
+                                                    coarse_opts=dict(tol=args.newton_tol,
+                                                                     gmres_m=args.gmres_m))
         U = Ud.cpu()
         res_ora = float(orc.residual(U, project=True).abs().max())
         base_info = {"base": args.base, "newton_stages": [[s_[0], s_[1]["newton_its"]]
@@ -125,6 +130,7 @@ def main(argv=None):
         log(f"steady state: oracle max|P F| = {res_ora:.3e}")
     v0 = ctx.project(torch.as_tensor(inputs.random_fields(ctx.n, 5000)).cuda())
     out = {"grid": [n] * 3, "grid_kind": "tanh", "s": 1.5, "span_bc": args.bc, "Gr": args.gr,
+           "gmres_m": args.gmres_m,
            "Pr": args.pr, "k": args.k, "m": args.m, "keep": args.keep, "tol": args.tol,
            "chebyshev": args.chebyshev}
     out.update(base_info)
