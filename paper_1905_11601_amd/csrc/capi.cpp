@@ -366,11 +366,12 @@ fvk_status fvk_create(fvk_ctx **out, int nx, int ny, int nz, int grid_kind, doub
     if ((st = dalloc(ctx, reinterpret_cast<double **>(&w.tb1), nc)) != FVK_OK) goto bad;
     if ((st = dalloc(ctx, &w.vtmp, nvec(ctx))) != FVK_OK) goto bad;
     if ((st = dalloc(ctx, &w.vtmp2, nvec(ctx))) != FVK_OK) goto bad;
-    // block partials: multi-dot (<= 512 vectors) and the lagged step's
-    // two-vector dots (<= 2 (j + 2) <= 512 rows)
+    // block partials: multi-dot (<= 1024 vectors) and the lagged step's
+    // two-vector dots (2 (j + 2) <= 1024 rows: Krylov dimensions up to 510,
+    // beyond the 400 of fvk_linear_solve / newton_step's GMRES(m))
     w.red_len = std::max<size_t>(size_t(correct_blocks(g)),
                                  size_t(std::max(multidot_blocks(nvec(ctx)),
-                                                 multidot2_blocks(nvec(ctx)))) * 512);
+                                                 multidot2_blocks(nvec(ctx)))) * 1024);
     if ((st = dalloc(ctx, &w.red, w.red_len)) != FVK_OK) goto bad;
     if ((st = dalloc(ctx, &w.dev_scalars, 4096)) != FVK_OK) goto bad;
     if ((st = dalloc(ctx, &w.ring, size_t(kRing) * correct_blocks(g))) != FVK_OK) goto bad;

@@ -420,3 +420,26 @@ def test_psi_projection(fvk, n, kind, s, axis):
     xd = dev(x)
     ctx.lib.fvk_psi_projection(ctx.h, fvk._ptr(xd), axis, fvk._ptr(xd), None)   # in place
     assert rel_err(xd[:3], torch.stack(ref)) < TOL
+
+
+def test_arnoldi_step_lagged_long_basis(fvk):
+    """The lagged step beyond 255 basis vectors (the GMRES(400) range of the
+    Newton linear solves): 300 steps on a 10 x 9 x 11 grid (constraint
+    subspace of ~2,000 dimensions) keep the basis orthonormal, and the
+    Arnoldi relation A v_j = sum_q H[q, j] v_q holds for the last columns."""
+    print("case arnoldi lagged 300 steps", flush=True)
+    g, orc, ctx = setup((10, 9, 11), TANH, 1.5, 0)
+    U = dev(base(g, 0))
+    m = 300
+    V = torch.zeros(m + 1, ctx.N, dtype=torch.float64, device="cuda")
+    V[0] = dev(krylov_input(g, orc, 5000)).reshape(-1)
+    H = np.zeros((m + 1, m))
+    for j in range(m):
+        ctx.arnoldi_step_lagged(U, V, j, H)
+    ctx.arnoldi_finish(V, m, H)
+    G = (V @ V.T).cpu().numpy()
+    assert np.max(np.abs(G - np.eye(m + 1))) < 1e-11
+    for j in (m - 2, m - 1):
+        Av = ctx.simple_krylov_vec(U, V[j].reshape(ctx.shape4).contiguous()).reshape(-1)
+        rhs = torch.as_tensor(H[:j + 2, j], device="cuda") @ V[:j + 2]
+        assert rel_err(Av, rhs) < 1e-9
