@@ -425,7 +425,7 @@ def test_psi_projection(fvk, n, kind, s, axis):
 def test_arnoldi_step_lagged_long_basis(fvk):
     """The lagged step beyond 255 basis vectors (the GMRES(400) range of the
     Newton linear solves): 300 steps on a 10 x 9 x 11 grid (constraint
-    subspace of ~2,000 dimensions) keep the basis orthonormal, and the
+    subspace of ~2,700 dimensions) keep the basis orthonormal, and the
     Arnoldi relation A v_j = sum_q H[q, j] v_q holds for the last columns."""
     print("case arnoldi lagged 300 steps", flush=True)
     g, orc, ctx = setup((10, 9, 11), TANH, 1.5, 0)
