@@ -327,7 +327,8 @@ fvk_status fvk_basis_rotate(fvk_ctx *ctx, double *V, size_t ldv, int m, const do
 
 typedef struct {
     double tol;             /* stop when max |P F| < tol (default 1e-10)          */
-    int gmres_m;            /* GMRES restart length (100, Sec. 3.1)               */
+    int gmres_m;            /* GMRES restart length (100, Sec. 3.1; 1 .. 400,
+                               else FVK_EINVAL)                                   */
     int gmres_max_restarts; /* cap on GMRES(m) cycles per Newton step             */
     double sat_ratio;       /* GMRES saturated when a cycle reduces |r| by less
                                than this factor (0.9)                             */
