@@ -13,7 +13,7 @@ the ~10^4 Arnoldi steps a large grid needs).  Mixed-precision eigenvalues are
 also compared with the FP64 ones.  One JSON line on stdout (and in --out).
 
     python tests/certify_eigs.py --n 256 --bc CC --k 4 --m 100 --prec both \\
-        --out gpurun_out/cert_256_CC.json
+        --out cert_256_CC.json
 
 Test infrastructure: it imports the oracle, so it lives under tests/.
 """
